@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the fan-beam renderer on one MI355X.
+
+Workload (one "step" = the whole hot path once): a batch of B probe poses
+over the 256^3 (1 mm) brain-like impedance volume, each pose a 70 deg fan of
+256 rays x 1024 samples (ds = 0.25 mm) with in-system attenuation, speckle
+and depth-dependent blur; the step renders every pose, forms the MSE loss
+against per-pose targets, and runs the hand-written adjoint to dL/dZ (full
+volume, cleared every step) and dL/dpose -- one captured HIP graph per step
+(the batched fused form).  Synthetic, seeded inputs.
+
+Printed: one JSON line with ray-samples/s of that step, the same for the
+plain per-pose form and the forward-only form, the roofline of the dominant
+kernel (HIP events on the launch stream) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--poses B] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, reps, stream_events):
+    """Average ms of fn() over reps launches, HIP events on the current stream."""
+    import torch
+    start, stop = stream_events
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        fn()
+    stop.record()
+    stop.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def cpu_baseline(case, budget_s: float):
+    """FP64 oracle (forward + MSE + adjoint) on the first poses of the batch,
+    until budget_s seconds of work or the whole batch."""
+    from oracle import oracle as O
+    from tests import helpers as H
+
+    vol = H.oracle_volume(case)
+    ph = H.oracle_physics(case.phys)
+    gV = np.zeros_like(vol.Z)
+    t0 = time.perf_counter()
+    done = 0
+    samples = 0
+    for p, f in enumerate(case.fans):
+        of = H.oracle_fan(f)
+        pose = case.poses[p].astype(np.float64)
+        img = O.render(vol, pose, of, ph)
+        _, g = O.mse_loss_grad(img, np.zeros_like(img))     # the target does not change the cost
+        gv, gp = O.backward(vol, pose, of, ph, g)
+        gV += gv
+        done += 1
+        samples += f.n_rays * f.n_samples
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": samples / dt, "unit": "ray-samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of {len(case.fans)} poses (256x1024 each), FP64 forward + MSE + adjoint "
+                      f"(dL/dZ and dL/dpose), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--poses", type=int, default=64)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this renderer build has no multi-GPU path "
+              "(poses shard with no communication; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2508_06768_amd import synth
+    from paper_2508_06768_amd.render import (FusedStep, Geometry, footprint_voxels, render,
+                                             render_backward)
+
+    dev = torch.device("cuda:0")
+    B = args.poses
+    log(f"bench: building workload, {B} poses x 256 rays x 1024 samples on 256^3")
+    case = synth.case_batched_c2(B=B)
+    geom = Geometry(case.Z.shape, case.spacing, case.origin, case.fans, case.phys)
+    Z = torch.from_numpy(case.Z).to(dev)
+    poses = torch.from_numpy(case.poses).to(dev)
+    tposes = torch.from_numpy(case.extra["target_poses"]).to(dev)
+    target = render(Z, tposes, geom).clone()
+    N = geom.total
+    log("bench: targets rendered")
+
+    step = FusedStep(geom, zero_grad_z=True)
+    gZ = torch.zeros_like(Z)
+    gp = torch.empty((B, 6), device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    def fused():
+        step.step(Z, poses, target, loss=loss, grad_Z=gZ, grad_pose=gp)
+
+    for _ in range(args.warmup):
+        fused()
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+    t0 = time.perf_counter()
+    ms = timed(fused, args.steps, ev)
+    wall = time.perf_counter() - t0
+    value = N / (ms * 1e-3)
+    log(f"bench: fused batched step {ms:.3f} ms ({value:.3e} ray-samples/s)")
+
+    # forward only, batched (render + blur)
+    out = torch.empty(N, device=dev)
+    ws_f = geom.workspace(False, dev)
+    ms_fwd = timed(lambda: render(Z, poses, geom, out=out, ws=ws_f), max(5, args.steps), ev)
+    log(f"bench: forward batched {ms_fwd:.3f} ms")
+
+    # plain form: one launch sequence per pose, no graph
+    plain_ms = None
+    if not args.no_plain:
+        singles = []
+        for p in range(B):
+            g1 = Geometry(case.Z.shape, case.spacing, case.origin, [case.fans[p]], case.phys)
+            s1 = FusedStep(g1, zero_grad_z=False, graph=False)
+            singles.append((s1, poses[p:p + 1].contiguous(), target[geom.offsets[p]:geom.offsets[p + 1]]))
+        gp1 = torch.empty((1, 6), device=dev)
+
+        def plain():
+            gZ.zero_()
+            for s1, p1, t1 in singles:
+                s1.step(Z, p1, t1, loss=loss, grad_Z=gZ, grad_pose=gp1)
+
+        plain()
+        plain_ms = timed(plain, max(2, args.steps // 4), ev)
+        log(f"bench: plain per-pose step {plain_ms:.3f} ms")
+
+    # dominant kernels alone (same kernels as inside the step): blur off so a
+    # call launches exactly one kernel
+    import copy
+    ph1 = copy.copy(case.phys)
+    ph1.blur_on = False
+    g_nb = Geometry(case.Z.shape, case.spacing, case.origin, case.fans, ph1)
+    ws_b = g_nb.workspace(True, dev)
+    ms_k_fwd = timed(lambda: render(Z, poses, g_nb, out=out), 10, ev)
+    gsrc = torch.randn(N, device=dev) * 1e-6
+    ms_k_bwd = timed(lambda: render_backward(Z, poses, g_nb, gsrc, want_Z=True, want_pose=False, grad_Z=gZ,
+                                             ws=ws_b), 10, ev)
+    vfp = footprint_voxels(poses, geom)
+    n_vox = int(np.prod(case.Z.shape))
+    bytes_fwd = 4.0 * N + 4.0 * vfp
+    bytes_bwd = 4.0 * N + 4.0 * vfp + 8.0 * vfp
+    kern = {
+        "forward": {"ms": ms_k_fwd, "alg_bytes": bytes_fwd, "GBs": bytes_fwd / (ms_k_fwd * 1e-3) / 1e9},
+        "adjoint": {"ms": ms_k_bwd, "alg_bytes": bytes_bwd, "GBs": bytes_bwd / (ms_k_bwd * 1e-3) / 1e9},
+    }
+    dom = "adjoint" if ms_k_bwd >= ms_k_fwd else "forward"
+    log(f"bench: kernels {json.dumps(kern)} footprint voxels {vfp}")
+
+    cpu = None
+    if not args.no_cpu:
+        log("bench: timing the FP64 CPU oracle")
+        cpu = cpu_baseline(case, args.cpu_budget)
+
+    res = {
+        "metric": "ray-samples/s, batched fused forward+MSE+adjoint (256^3 vol, 256 rays x 1024 samples/pose)",
+        "value": value,
+        "unit": "ray-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{B} poses x 256 rays x 1024 samples, 70 deg fans over a 256^3 1 mm brain-like "
+                        "impedance volume, in-system attenuation, speckle + depth blur, fwd + MSE + adjoint "
+                        "(dL/dZ full volume, dL/dpose), one HIP graph per step",
+            "poses": B, "ray_samples_per_step": N, "footprint_voxels": vfp, "volume_voxels": n_vox,
+        },
+        "forward_batched": {"ms": ms_fwd, "value": N / (ms_fwd * 1e-3)},
+        "plain_per_pose": None if plain_ms is None else {"ms": plain_ms, "value": N / (plain_ms * 1e-3)},
+        "kernels": kern,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": kern[dom]["GBs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": kern[dom]["GBs"] / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "cpu_baseline": cpu,
+        "wall_s_timed": wall,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * diffus.h -- C ABI of the MI355X (gfx950) DiffUS fan-beam renderer.
+ *
+ * The renderer follows arXiv 2508.06768 ("DiffUS: Differentiable Ultrasound
+ * Rendering from Volumetric Imaging"):
+ *   - Sec. 2.1, Eq. 1: interface coefficients R = |Z2-Z1|/(Z1+Z2),
+ *     T = 2 Z2/(Z1+Z2) (a signed-R mode is offered as an option);
+ *   - Sec. 2.1: straight rays, uniform attenuation;
+ *   - Sec. 2.3, Eq. 2-4: coupled forward/backward amplitudes per ray, solved
+ *     for every truncation depth k (Sec. 2.4) -- here by an O(S) composition
+ *     of the per-interface 2x2 transfer maps, computed in FP64;
+ *   - Sec. 2.4: fan of rays from one virtual transducer, pixel = first
+ *     difference of the depth-resolved echo, optional depth-dependent speckle
+ *     and lateral blur;
+ *   - Sec. 1 / abstract: differentiable, for registration and reconstruction:
+ *     gradients with respect to the impedance volume and the probe pose.
+ *
+ * Conventions
+ *   Volume Z[nz][ny][nx] FP32 (MRayl, > 0, finite), x fastest.  Voxel (i,j,k)
+ *   has its centre at origin + (i hx, j hy, k hz) mm.  Sampling is trilinear
+ *   with clamp-to-edge.
+ *   Pose p: 6 FP32 values (t_x, t_y, t_z [mm], w_x, w_y, w_z [rad]) mapping a
+ *   probe point q to world t + R(w) q, R(w) = exp([w]x).  In the probe frame
+ *   ray j of a fan of n rays has direction (sin th_j, 0, cos th_j),
+ *   th_j = -A/2 + j A/(n-1) (th = 0 when n = 1); sample k sits at
+ *   s_k = r0 + k ds.
+ *   B-mode image of pose p: FP32 [n_rays][n_samples] starting at element
+ *   fans[p].out_offset of the output array; pixel k of a ray is the echo of
+ *   the interface between samples k-1 and k (pixel 0 is 0).
+ *
+ * Memory and streams
+ *   Pointers named Z, poses, bmode, grad_*, target, ws, counters, out are
+ *   DEVICE pointers; dus_volume / dus_fan / dus_physics arguments are HOST
+ *   pointers.  The caller owns every buffer, including the workspace; the
+ *   library never allocates device memory in a render call and never
+ *   synchronises the stream: all work is enqueued on `stream` (a
+ *   hipStream_t; NULL is the default stream).  Plans (dus_plan_*) own a
+ *   captured HIP graph and a private capture stream.
+ *
+ * Errors
+ *   Host-side validation runs before anything is enqueued; on failure a
+ *   negative dus_status is returned and nothing is enqueued.  HIP failures
+ *   return DUS_EHIP; dus_last_error() gives the detail (per thread).
+ *   Numerical hazards are not errors: NaN/Inf propagate.  With the |R|
+ *   convention of Eq. 1 the per-ray system can approach singularity (a
+ *   pole of the echo); ray_min_pivot reports how close each ray came.
+ */
+#ifndef DIFFUS_H
+#define DIFFUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DUS_OK = 0,
+    DUS_EINVAL = -1,       /* null pointer, bad enum, non-finite parameter */
+    DUS_ESHAPE = -2,       /* sizes out of range or inconsistent */
+    DUS_EWORKSPACE = -3,   /* workspace missing or too small */
+    DUS_EHIP = -4,         /* a HIP runtime call failed */
+    DUS_EUNSUPPORTED = -5  /* valid request this build does not handle */
+} dus_status;
+
+enum { DUS_REFL_ABS = 0, DUS_REFL_SIGNED = 1 };
+enum { DUS_ATTEN_IN_SYSTEM = 0, DUS_ATTEN_POST_HOC = 1, DUS_ATTEN_OFF = 2 };
+
+/* Limits checked by validation. */
+#define DUS_MAX_SAMPLES 16384      /* samples per ray */
+#define DUS_MAX_RAYS 65536         /* rays per fan */
+#define DUS_MAX_BLUR_RADIUS 32     /* ceil(3 * max(sigma0, sigma1)) */
+
+typedef struct {
+    int32_t nx, ny, nz;            /* voxels per axis, each >= 2 */
+    float spacing_mm[3];           /* > 0 */
+    float origin_mm[3];            /* world position of voxel (0,0,0)'s centre */
+} dus_volume;
+
+typedef struct {
+    int32_t n_rays;                /* >= 0 (0: the pose renders nothing) */
+    int32_t n_samples;             /* >= 0, <= DUS_MAX_SAMPLES */
+    float aperture_rad;            /* full fan angle, finite */
+    float ds_mm;                   /* depth step, > 0 */
+    float r0_mm;                   /* apex-to-first-sample distance, finite */
+    int32_t speckle_id;            /* speckle stream of this fan (counter word 2) */
+    int64_t out_offset;            /* element offset of this pose's image */
+} dus_fan;
+
+typedef struct {
+    float alpha_db_cm_mhz;         /* attenuation, >= 0 */
+    float f_mhz;                   /* centre frequency, >= 0 */
+    int32_t refl_mode;             /* DUS_REFL_ABS (Eq. 1 as printed) or DUS_REFL_SIGNED */
+    int32_t atten_mode;            /* DUS_ATTEN_* */
+    int32_t speckle_on;            /* 0/1 */
+    int32_t spk_cell;              /* radial speckle cell, samples, >= 4 */
+    float spk_Ar, spk_gamma;       /* radial amplitude and depth exponent */
+    float spk_Ag0, spk_Ag1;        /* granular amplitude at zero and full depth */
+    int32_t blur_on;               /* 0/1 */
+    float blur_sigma0, blur_sigma1;/* lateral blur sigma (rays) at first/last depth */
+    int32_t reserved;              /* must be 0 */
+    uint64_t seed;                 /* Philox key = (seed low, seed high) */
+} dus_physics;
+
+/* Status text and the last HIP error detail of the calling thread. */
+const char *dus_status_string(int status);
+const char *dus_last_error(void);
+int dus_version(void);
+
+/*
+ * Workspace size in bytes for dus_render_bmode (with_backward = 0) or for
+ * dus_render_bmode_backward (with_backward = 1) with these arguments.
+ * Returns a negative dus_status on invalid arguments.
+ */
+int64_t dus_workspace_bytes(const dus_volume *vol, const dus_fan *fans, int32_t n_poses,
+                            const dus_physics *phys, int32_t with_backward);
+
+/*
+ * Forward render (Sec. 2.3-2.4) of n_poses fans in one batched launch.
+ *   Z        device, FP32 [nz][ny][nx]
+ *   poses    device, FP32 [n_poses][6]
+ *   fans     host, n_poses records; output blocks must not overlap
+ *   bmode    device, FP32; pose p writes [n_rays][n_samples] at out_offset
+ *   ray_min_pivot  device, FP32 [total rays] in pose-major ray order, or
+ *            NULL.  Per ray: min_k |P_{k+1}[1][1] / P_k[1][1]|, the pivots of
+ *            the top-down elimination of the truncated systems (ratios of
+ *            consecutive determinants of Eq. 4); 0 means a singular system.
+ *   ws       device workspace of at least dus_workspace_bytes(..., 0) bytes
+ *            (may be NULL when that size is 0)
+ */
+int dus_render_bmode(const float *Z, const dus_volume *vol, const float *poses,
+                     const dus_fan *fans, int32_t n_poses, const dus_physics *phys,
+                     float *bmode, float *ray_min_pivot, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * Exact gradient of dus_render_bmode (hand-written adjoint).
+ *   grad_bmode  device FP32, dL/d(bmode), same layout as bmode
+ *   grad_Z      device FP32 [nz][ny][nx] or NULL: dL/dZ is ADDED (+=)
+ *   grad_pose   device FP32 [n_poses][6] or NULL: dL/dpose, OVERWRITTEN
+ *   ws          at least dus_workspace_bytes(..., 1) bytes
+ * The forward is recomputed inside; nothing from dus_render_bmode is reused.
+ * grad_Z accumulation uses FP32 atomics (order-dependent rounding).
+ */
+int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float *poses,
+                              const dus_fan *fans, int32_t n_poses, const dus_physics *phys,
+                              const float *grad_bmode, float *grad_Z, float *grad_pose,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Philox4x32-10 (Salmon et al., SC'11), the generator of the speckle
+ * multipliers (Sec. 2.4).  counters: device uint32 [n][4]; out: device
+ * uint32 [n][4]; key = (seed low 32 bits, seed high 32 bits).
+ */
+int dus_philox4x32_10(const uint32_t *counters, int64_t n, uint64_t seed, uint32_t *out,
+                      void *stream);
+
+/*
+ * Per-pixel gain applied to the raw echo of one fan: post-hoc attenuation
+ * (atten_mode POST_HOC) times the speckle multiplier (speckle_on), Sec. 2.4.
+ * out: device FP32 [n_rays][n_samples].
+ */
+int dus_pixel_gain(const dus_fan *fan, const dus_physics *phys, float *out, void *stream);
+
+/*
+ * Footprint of the rendering: mask[v] = 1 for every voxel v that is a corner
+ * of the trilinear stencil of some sample of some ray (other entries are left
+ * untouched).  mask: device uint8 [nz][ny][nx].  Used to count the distinct
+ * voxels a render must read (the compulsory volume traffic).
+ */
+int dus_footprint_mask(const dus_volume *vol, const float *poses, const dus_fan *fans,
+                       int32_t n_poses, uint8_t *mask, void *stream);
+
+/*
+ * Batched fused step: forward, loss = sum over poses of mean((I - target)^2),
+ * adjoint.  A plan fixes the volume shape, the fans and the physics; each
+ * dus_plan_step replays one captured HIP graph on `stream`.
+ */
+typedef struct dus_plan dus_plan;
+
+enum {
+    DUS_PLAN_POSE_ONLY = 1,   /* grad_Z is neither needed nor touched */
+    DUS_PLAN_ZERO_GRAD_Z = 2, /* the step clears grad_Z itself (fill kernel) */
+    DUS_PLAN_NO_GRAPH = 4     /* launch eagerly instead of replaying a graph */
+};
+
+/* Ray-to-wavefront schedule; 0 fields select the library default. */
+typedef struct {
+    int32_t fwd_chunk;        /* interfaces per lane per tile, forward: 4, 8 or 16 */
+    int32_t bwd_chunk;        /* same for the adjoint: 4 or 8 */
+    int32_t xcd_group;        /* consecutive rays kept on one XCD: 1..64 */
+    int32_t reserved;
+} dus_schedule;
+
+int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans,
+                    int32_t n_poses, const dus_physics *phys, int32_t flags);
+int64_t dus_plan_workspace_bytes(const dus_plan *plan);
+int dus_plan_set_schedule(dus_plan *plan, const dus_schedule *sched);
+int dus_plan_get_schedule(const dus_plan *plan, dus_schedule *sched);
+/*
+ *   target   device FP32, same layout as bmode
+ *   bmode    device FP32 or NULL: the rendered image is also written
+ *   loss     device FP64 scalar or NULL: receives the loss (overwritten)
+ *   grad_Z   device FP32 or NULL (+=; cleared first with DUS_PLAN_ZERO_GRAD_Z)
+ *   grad_pose device FP32 [n_poses][6] or NULL (overwritten)
+ */
+int dus_plan_step(dus_plan *plan, const float *Z, const float *poses, const float *target,
+                  float *bmode, double *loss, float *grad_Z, float *grad_pose,
+                  void *ws, size_t ws_bytes, void *stream);
+void dus_plan_destroy(dus_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIFFUS_H */

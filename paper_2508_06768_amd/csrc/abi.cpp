@@ -1,0 +1,589 @@
+// Host side of the C ABI declared in include/diffus.h: argument validation,
+// workspace layout, fan tables for batched launches, and the captured-graph
+// plan of the fused forward + loss + adjoint step.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/diffus.h"
+#include "dus_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *what)
+{
+    g_last_error = what ? what : "";
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return DUS_EHIP;
+}
+
+#define DUS_HIP(call, where)                                \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, where);   \
+    } while (0)
+
+bool finite_f(float x) { return isfinite(x) != 0; }
+
+constexpr int kDefaultFwdChunk = 8;
+constexpr int kDefaultBwdChunk = 8;
+constexpr int kDefaultXcdGroup = 16;
+
+int check_volume(const dus_volume *v)
+{
+    if (!v) return fail(DUS_EINVAL, "volume descriptor is NULL");
+    if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(DUS_ESHAPE, "each volume axis needs >= 2 voxels");
+    const long long n = (long long)v->nx * v->ny * v->nz;
+    if (n >= (1ll << 31)) return fail(DUS_ESHAPE, "volume has 2^31 voxels or more");
+    for (int a = 0; a < 3; ++a) {
+        if (!finite_f(v->spacing_mm[a]) || !(v->spacing_mm[a] > 0.0f))
+            return fail(DUS_EINVAL, "voxel spacing must be finite and > 0");
+        if (!finite_f(v->origin_mm[a])) return fail(DUS_EINVAL, "volume origin must be finite");
+    }
+    return DUS_OK;
+}
+
+int check_physics(const dus_physics *p)
+{
+    if (!p) return fail(DUS_EINVAL, "physics descriptor is NULL");
+    if (p->refl_mode != DUS_REFL_ABS && p->refl_mode != DUS_REFL_SIGNED)
+        return fail(DUS_EINVAL, "refl_mode must be DUS_REFL_ABS or DUS_REFL_SIGNED");
+    if (p->atten_mode < DUS_ATTEN_IN_SYSTEM || p->atten_mode > DUS_ATTEN_OFF)
+        return fail(DUS_EINVAL, "atten_mode out of range");
+    if (!finite_f(p->alpha_db_cm_mhz) || p->alpha_db_cm_mhz < 0.0f || !finite_f(p->f_mhz) || p->f_mhz < 0.0f)
+        return fail(DUS_EINVAL, "attenuation parameters must be finite and >= 0");
+    if (p->speckle_on != 0 && p->speckle_on != 1) return fail(DUS_EINVAL, "speckle_on must be 0 or 1");
+    if (p->blur_on != 0 && p->blur_on != 1) return fail(DUS_EINVAL, "blur_on must be 0 or 1");
+    if (p->reserved != 0) return fail(DUS_EINVAL, "reserved field must be 0");
+    if (p->speckle_on) {
+        if (p->spk_cell < 4 || p->spk_cell > (1 << 20)) return fail(DUS_EINVAL, "spk_cell must be in [4, 2^20]");
+        if (!finite_f(p->spk_Ar) || !finite_f(p->spk_gamma) || !finite_f(p->spk_Ag0) || !finite_f(p->spk_Ag1) ||
+            p->spk_gamma < 0.0f)
+            return fail(DUS_EINVAL, "speckle parameters must be finite, gamma >= 0");
+    }
+    if (p->blur_on) {
+        if (!finite_f(p->blur_sigma0) || !finite_f(p->blur_sigma1) || p->blur_sigma0 < 0.0f ||
+            p->blur_sigma1 < 0.0f)
+            return fail(DUS_EINVAL, "blur sigmas must be finite and >= 0");
+        const float smax = std::max(p->blur_sigma0, p->blur_sigma1);
+        if (ceilf(3.0f * smax) > (float)DUS_MAX_BLUR_RADIUS)
+            return fail(DUS_EUNSUPPORTED, "blur radius ceil(3 sigma) exceeds DUS_MAX_BLUR_RADIUS");
+    }
+    return DUS_OK;
+}
+
+int check_fans(const dus_fan *fans, int32_t n_poses)
+{
+    if (n_poses < 0) return fail(DUS_ESHAPE, "n_poses < 0");
+    if (n_poses > 0 && !fans) return fail(DUS_EINVAL, "fans is NULL");
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    for (int i = 0; i < n_poses; ++i) {
+        const dus_fan &f = fans[i];
+        if (f.n_rays < 0 || f.n_rays > DUS_MAX_RAYS) return fail(DUS_ESHAPE, "n_rays out of range");
+        if (f.n_samples < 0 || f.n_samples > DUS_MAX_SAMPLES) return fail(DUS_ESHAPE, "n_samples out of range");
+        if (!finite_f(f.aperture_rad) || !finite_f(f.r0_mm) || !finite_f(f.ds_mm) || !(f.ds_mm > 0.0f))
+            return fail(DUS_EINVAL, "fan geometry must be finite with ds > 0");
+        if (f.out_offset < 0) return fail(DUS_ESHAPE, "out_offset < 0");
+        const int64_t n = (int64_t)f.n_rays * f.n_samples;
+        if (n > 0) spans.push_back({f.out_offset, f.out_offset + n});
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return fail(DUS_ESHAPE, "output blocks of two poses overlap");
+    return DUS_OK;
+}
+
+int64_t image_extent(const dus_fan *fans, int32_t n_poses)
+{
+    int64_t e = 0;
+    for (int i = 0; i < n_poses; ++i) {
+        const int64_t n = (int64_t)fans[i].n_rays * fans[i].n_samples;
+        if (n > 0) e = std::max(e, fans[i].out_offset + n);
+    }
+    return e;
+}
+
+dus::VolArgs vol_args(const float *Z, const dus_volume *v)
+{
+    dus::VolArgs a{};
+    a.Z = Z;
+    a.nx = v->nx;
+    a.ny = v->ny;
+    a.nz = v->nz;
+    for (int i = 0; i < 3; ++i) {
+        a.h[i] = v->spacing_mm[i];
+        a.o[i] = v->origin_mm[i];
+    }
+    return a;
+}
+
+dus::PhysArgs phys_args(const dus_physics *p)
+{
+    dus::PhysArgs a{};
+    a.alpha = p->alpha_db_cm_mhz;
+    a.freq = p->f_mhz;
+    a.refl = p->refl_mode;
+    a.atten = p->atten_mode;
+    a.speckle = p->speckle_on;
+    a.cell = p->spk_cell > 0 ? p->spk_cell : 8;
+    a.Ar = p->spk_Ar;
+    a.gam = p->spk_gamma;
+    a.Ag0 = p->spk_Ag0;
+    a.Ag1 = p->spk_Ag1;
+    a.blur = p->blur_on;
+    a.s0 = p->blur_sigma0;
+    a.s1 = p->blur_sigma1;
+    a.key0 = (uint32_t)(p->seed & 0xffffffffull);
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.blur_rmax = p->blur_on ? (int)ceilf(3.0f * std::max(p->blur_sigma0, p->blur_sigma1)) : 0;
+    if (a.blur_rmax > DUS_MAX_BLUR_RADIUS) a.blur_rmax = DUS_MAX_BLUR_RADIUS;
+    return a;
+}
+
+// Fan tables of at most kMaxFans fans, each sorted longest ray first so the
+// hardware dispatcher starts the longest rays first.
+std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses)
+{
+    std::vector<int> pivot_begin(n_poses + 1, 0);
+    for (int i = 0; i < n_poses; ++i) pivot_begin[i + 1] = pivot_begin[i] + std::max(0, fans[i].n_rays);
+    std::vector<int> order;
+    for (int i = 0; i < n_poses; ++i)
+        if (fans[i].n_rays > 0 && fans[i].n_samples > 0) order.push_back(i);
+    std::vector<dus::FanTable> out;
+    for (size_t g0 = 0; g0 < order.size(); g0 += dus::kMaxFans) {
+        std::vector<int> grp(order.begin() + g0, order.begin() + std::min(order.size(), g0 + dus::kMaxFans));
+        std::stable_sort(grp.begin(), grp.end(),
+                         [&](int a, int b) { return fans[a].n_samples > fans[b].n_samples; });
+        dus::FanTable t;
+        memset(&t, 0, sizeof(t));
+        t.n = (int)grp.size();
+        int rays = 0, blks = 0;
+        for (int q = 0; q < t.n; ++q) {
+            const dus_fan &f = fans[grp[q]];
+            dus::FanRec &r = t.f[q];
+            r.n_rays = f.n_rays;
+            r.n_samples = f.n_samples;
+            r.aperture = f.aperture_rad;
+            r.ds = f.ds_mm;
+            r.r0 = f.r0_mm;
+            r.speckle_id = f.speckle_id;
+            r.out_offset = f.out_offset;
+            r.ray_begin = rays;
+            r.blk_begin = blks;
+            r.pose = grp[q];
+            r.pivot_begin = pivot_begin[grp[q]];
+            rays += f.n_rays;
+            blks += ((f.n_samples + 63) / 64) * ((f.n_rays + 15) / 16);
+        }
+        t.total_rays = rays;
+        t.total_blur_blocks = blks;
+        out.push_back(t);
+    }
+    return out;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    size_t pre = 0, pre_bytes = 0;     // pre-blur image (forward with blur)
+    size_t eb = 0, eb_bytes = 0;       // blur-transposed dL/dI (adjoint with blur)
+    size_t res = 0, res_bytes = 0;     // MSE residual (plan with blur)
+    size_t acc = 0, acc_bytes = 0;     // pose accumulators
+    size_t total = 0;
+};
+
+WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int mode)
+{
+    // mode 0: forward, 1: backward, 2: plan step
+    WsLayout L;
+    const size_t img = (size_t)image_extent(fans, n_poses) * sizeof(float);
+    size_t off = 0;
+    if (p->blur_on && (mode == 0 || mode == 2)) {
+        L.pre = off;
+        L.pre_bytes = img;
+        off = align_up(off + img);
+    }
+    if (p->blur_on && (mode == 1 || mode == 2)) {
+        L.eb = off;
+        L.eb_bytes = img;
+        off = align_up(off + img);
+    }
+    if (p->blur_on && mode == 2) {
+        L.res = off;
+        L.res_bytes = img;
+        off = align_up(off + img);
+    }
+    if (mode == 1 || mode == 2) {
+        L.acc = off;
+        L.acc_bytes = (size_t)std::max(n_poses, 1) * dus::kPoseAcc * sizeof(double);
+        off = align_up(off + L.acc_bytes);
+    }
+    L.total = off;
+    return L;
+}
+
+int check_ws(void *ws, size_t ws_bytes, size_t need)
+{
+    if (need == 0) return DUS_OK;
+    if (!ws) return fail(DUS_EWORKSPACE, "workspace is NULL but the call needs one");
+    if (ws_bytes < need) return fail(DUS_EWORKSPACE, "workspace too small");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(DUS_EWORKSPACE, "workspace must be 256-byte aligned");
+    return DUS_OK;
+}
+
+int check_common(const float *Z, const dus_volume *vol, const float *poses, const dus_fan *fans,
+                 int32_t n_poses, const dus_physics *phys)
+{
+    int s;
+    if ((s = check_volume(vol)) != DUS_OK) return s;
+    if ((s = check_physics(phys)) != DUS_OK) return s;
+    if ((s = check_fans(fans, n_poses)) != DUS_OK) return s;
+    if (n_poses > 0 && image_extent(fans, n_poses) > 0) {
+        if (!Z) return fail(DUS_EINVAL, "Z is NULL");
+        if (!poses) return fail(DUS_EINVAL, "poses is NULL");
+    }
+    return DUS_OK;
+}
+
+// ---- enqueue helpers shared by the direct calls and the plan ----
+struct Sched {
+    int fwd_chunk = kDefaultFwdChunk;
+    int bwd_chunk = kDefaultBwdChunk;
+    int xcd_group = kDefaultXcdGroup;
+};
+
+int enqueue_forward(const Sched &sc, const dus::VolArgs &va, const dus::PhysArgs &pa,
+                    const std::vector<dus::FanTable> &tabs, const float *poses, float *out,
+                    float *min_pivot, hipStream_t st)
+{
+    for (const auto &t : tabs)
+        DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, out, min_pivot, 0, st),
+                "forward kernel launch");
+    return DUS_OK;
+}
+
+}  // namespace
+
+struct dus_plan {
+    dus_volume vol;
+    std::vector<dus_fan> fans;
+    dus_physics phys;
+    int32_t flags;
+    Sched sched;
+    std::vector<dus::FanTable> tabs;
+    WsLayout ws;
+    int64_t extent;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void *key[9] = {};
+    size_t key_ws_bytes = 0;
+    int device = -1;
+};
+
+extern "C" {
+
+const char *dus_status_string(int s)
+{
+    switch (s) {
+    case DUS_OK: return "ok";
+    case DUS_EINVAL: return "invalid argument";
+    case DUS_ESHAPE: return "invalid shape";
+    case DUS_EWORKSPACE: return "workspace missing or too small";
+    case DUS_EHIP: return "HIP runtime error";
+    case DUS_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *dus_last_error(void) { return g_last_error.c_str(); }
+
+int dus_version(void) { return 1; }
+
+int64_t dus_workspace_bytes(const dus_volume *vol, const dus_fan *fans, int32_t n_poses,
+                            const dus_physics *phys, int32_t with_backward)
+{
+    int s;
+    if ((s = check_volume(vol)) != DUS_OK) return s;
+    if ((s = check_physics(phys)) != DUS_OK) return s;
+    if ((s = check_fans(fans, n_poses)) != DUS_OK) return s;
+    return (int64_t)layout(fans, n_poses, phys, with_backward ? 1 : 0).total;
+}
+
+int dus_render_bmode(const float *Z, const dus_volume *vol, const float *poses, const dus_fan *fans,
+                     int32_t n_poses, const dus_physics *phys, float *bmode, float *ray_min_pivot,
+                     void *ws, size_t ws_bytes, void *stream)
+{
+    int s;
+    if ((s = check_common(Z, vol, poses, fans, n_poses, phys)) != DUS_OK) return s;
+    const int64_t extent = image_extent(fans, n_poses);
+    if (extent > 0 && !bmode) return fail(DUS_EINVAL, "bmode is NULL");
+    const WsLayout L = layout(fans, n_poses, phys, 0);
+    if ((s = check_ws(ws, ws_bytes, L.total)) != DUS_OK) return s;
+    if (extent == 0) return DUS_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const auto tabs = build_tables(fans, n_poses);
+    const dus::VolArgs va = vol_args(Z, vol);
+    const dus::PhysArgs pa = phys_args(phys);
+    Sched sc;
+    float *dst = phys->blur_on ? reinterpret_cast<float *>((char *)ws + L.pre) : bmode;
+    if ((s = enqueue_forward(sc, va, pa, tabs, poses, dst, ray_min_pivot, st)) != DUS_OK) return s;
+    if (phys->blur_on)
+        for (const auto &t : tabs) DUS_HIP(dus::launch_blur(false, pa, t, dst, bmode, st), "blur kernel launch");
+    return DUS_OK;
+}
+
+int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float *poses,
+                              const dus_fan *fans, int32_t n_poses, const dus_physics *phys,
+                              const float *grad_bmode, float *grad_Z, float *grad_pose, void *ws,
+                              size_t ws_bytes, void *stream)
+{
+    int s;
+    if ((s = check_common(Z, vol, poses, fans, n_poses, phys)) != DUS_OK) return s;
+    const int64_t extent = image_extent(fans, n_poses);
+    if (extent > 0 && !grad_bmode) return fail(DUS_EINVAL, "grad_bmode is NULL");
+    const WsLayout L = layout(fans, n_poses, phys, 1);
+    if ((s = check_ws(ws, ws_bytes, L.total)) != DUS_OK) return s;
+    if (!grad_Z && !grad_pose) return DUS_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    double *acc = reinterpret_cast<double *>((char *)ws + L.acc);
+    if (grad_pose) DUS_HIP(dus::launch_zero_f64(acc, (int64_t)n_poses * dus::kPoseAcc, st), "zero kernel launch");
+    if (extent > 0) {
+        const auto tabs = build_tables(fans, n_poses);
+        const dus::VolArgs va = vol_args(Z, vol);
+        const dus::PhysArgs pa = phys_args(phys);
+        Sched sc;
+        const float *src = grad_bmode;
+        if (phys->blur_on) {
+            float *eb = reinterpret_cast<float *>((char *)ws + L.eb);
+            for (const auto &t : tabs) DUS_HIP(dus::launch_blur(true, pa, t, grad_bmode, eb, st), "blur^T kernel launch");
+            src = eb;
+        }
+        for (const auto &t : tabs)
+            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, src, nullptr, grad_Z,
+                                         grad_pose ? acc : nullptr, nullptr, st),
+                    "adjoint kernel launch");
+    }
+    if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel launch");
+    return DUS_OK;
+}
+
+int dus_philox4x32_10(const uint32_t *counters, int64_t n, uint64_t seed, uint32_t *out, void *stream)
+{
+    if (n < 0) return fail(DUS_ESHAPE, "n < 0");
+    if (n == 0) return DUS_OK;
+    if (!counters || !out) return fail(DUS_EINVAL, "NULL pointer");
+    DUS_HIP(dus::launch_philox(counters, n, (uint32_t)(seed & 0xffffffffull), (uint32_t)(seed >> 32), out,
+                               reinterpret_cast<hipStream_t>(stream)),
+            "philox kernel launch");
+    return DUS_OK;
+}
+
+int dus_pixel_gain(const dus_fan *fan, const dus_physics *phys, float *out, void *stream)
+{
+    int s;
+    if ((s = check_physics(phys)) != DUS_OK) return s;
+    if ((s = check_fans(fan, 1)) != DUS_OK) return s;
+    if ((int64_t)fan->n_rays * fan->n_samples == 0) return DUS_OK;
+    if (!out) return fail(DUS_EINVAL, "out is NULL");
+    if (fan->n_samples > 65535 * 256) return fail(DUS_ESHAPE, "too many samples");
+    dus::FanRec r{};
+    r.n_rays = fan->n_rays;
+    r.n_samples = fan->n_samples;
+    r.aperture = fan->aperture_rad;
+    r.ds = fan->ds_mm;
+    r.r0 = fan->r0_mm;
+    r.speckle_id = fan->speckle_id;
+    DUS_HIP(dus::launch_pixel_gain(phys_args(phys), r, out, reinterpret_cast<hipStream_t>(stream)),
+            "gain kernel launch");
+    return DUS_OK;
+}
+
+int dus_footprint_mask(const dus_volume *vol, const float *poses, const dus_fan *fans, int32_t n_poses,
+                       uint8_t *mask, void *stream)
+{
+    int s;
+    if ((s = check_volume(vol)) != DUS_OK) return s;
+    if ((s = check_fans(fans, n_poses)) != DUS_OK) return s;
+    if (image_extent(fans, n_poses) == 0) return DUS_OK;
+    if (!poses || !mask) return fail(DUS_EINVAL, "NULL pointer");
+    const dus::VolArgs va = vol_args(nullptr, vol);
+    for (const auto &t : build_tables(fans, n_poses))
+        DUS_HIP(dus::launch_footprint(va, t, poses, mask, reinterpret_cast<hipStream_t>(stream)),
+                "footprint kernel launch");
+    return DUS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plan: batched fused forward + MSE + adjoint, replayed from a HIP graph
+// ---------------------------------------------------------------------------
+int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, int32_t n_poses,
+                    const dus_physics *phys, int32_t flags)
+{
+    if (!out) return fail(DUS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int s;
+    if ((s = check_volume(vol)) != DUS_OK) return s;
+    if ((s = check_physics(phys)) != DUS_OK) return s;
+    if ((s = check_fans(fans, n_poses)) != DUS_OK) return s;
+    if (flags & ~(DUS_PLAN_POSE_ONLY | DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH))
+        return fail(DUS_EINVAL, "unknown plan flag");
+    dus_plan *p = new (std::nothrow) dus_plan();
+    if (!p) return fail(DUS_EINVAL, "out of host memory");
+    p->vol = *vol;
+    p->fans.assign(fans, fans + n_poses);
+    p->phys = *phys;
+    p->flags = flags;
+    p->tabs = build_tables(fans, n_poses);
+    p->ws = layout(fans, n_poses, phys, 2);
+    p->extent = image_extent(fans, n_poses);
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "plan stream");
+    }
+    *out = p;
+    return DUS_OK;
+}
+
+int64_t dus_plan_workspace_bytes(const dus_plan *p)
+{
+    if (!p) return fail(DUS_EINVAL, "plan is NULL");
+    return (int64_t)p->ws.total;
+}
+
+static void plan_drop_graph(dus_plan *p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+int dus_plan_set_schedule(dus_plan *p, const dus_schedule *sc)
+{
+    if (!p || !sc) return fail(DUS_EINVAL, "NULL pointer");
+    Sched n;
+    n.fwd_chunk = sc->fwd_chunk ? sc->fwd_chunk : kDefaultFwdChunk;
+    n.bwd_chunk = sc->bwd_chunk ? sc->bwd_chunk : kDefaultBwdChunk;
+    n.xcd_group = sc->xcd_group ? sc->xcd_group : kDefaultXcdGroup;
+    if (n.fwd_chunk != 4 && n.fwd_chunk != 8 && n.fwd_chunk != 16) return fail(DUS_EINVAL, "fwd_chunk must be 4, 8 or 16");
+    if (n.bwd_chunk != 4 && n.bwd_chunk != 8) return fail(DUS_EINVAL, "bwd_chunk must be 4 or 8");
+    if (n.xcd_group < 1 || n.xcd_group > 64) return fail(DUS_EINVAL, "xcd_group must be in [1, 64]");
+    // the adjoint keeps one carry per tile in LDS: S <= 16384 for either chunk
+    p->sched = n;
+    plan_drop_graph(p);
+    return DUS_OK;
+}
+
+int dus_plan_get_schedule(const dus_plan *p, dus_schedule *sc)
+{
+    if (!p || !sc) return fail(DUS_EINVAL, "NULL pointer");
+    sc->fwd_chunk = p->sched.fwd_chunk;
+    sc->bwd_chunk = p->sched.bwd_chunk;
+    sc->xcd_group = p->sched.xcd_group;
+    sc->reserved = 0;
+    return DUS_OK;
+}
+
+static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const float *target, float *bmode,
+                        double *loss, float *grad_Z, float *grad_pose, void *ws, hipStream_t st)
+{
+    const dus::VolArgs va = vol_args(Z, &p->vol);
+    const dus::PhysArgs pa = phys_args(&p->phys);
+    const int n_poses = (int)p->fans.size();
+    double *acc = reinterpret_cast<double *>((char *)ws + p->ws.acc);
+    float *gZ = (p->flags & DUS_PLAN_POSE_ONLY) ? nullptr : grad_Z;
+    if (grad_pose) DUS_HIP(dus::launch_zero_f64(acc, (int64_t)n_poses * dus::kPoseAcc, st), "zero kernel");
+    if (loss) DUS_HIP(dus::launch_zero_f64(loss, 1, st), "zero kernel");
+    if (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z))
+        DUS_HIP(dus::launch_zero_f32(gZ, (int64_t)p->vol.nx * p->vol.ny * p->vol.nz, st), "zero kernel");
+    const Sched &sc = p->sched;
+    if (p->phys.blur_on) {
+        float *pre = reinterpret_cast<float *>((char *)ws + p->ws.pre);
+        float *res = reinterpret_cast<float *>((char *)ws + p->ws.res);
+        float *eb = reinterpret_cast<float *>((char *)ws + p->ws.eb);
+        int s;
+        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, pre, nullptr, st)) != DUS_OK) return s;
+        for (const auto &t : p->tabs)
+            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, loss, st), "blur/loss kernel");
+        for (const auto &t : p->tabs) DUS_HIP(dus::launch_blur(true, pa, t, res, eb, st), "blur^T kernel");
+        if (gZ || grad_pose)
+            for (const auto &t : p->tabs)
+                DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, nullptr, gZ,
+                                             grad_pose ? acc : nullptr, nullptr, st),
+                        "adjoint kernel");
+    } else {
+        if (bmode) {
+            int s;
+            if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st)) != DUS_OK) return s;
+        }
+        for (const auto &t : p->tabs)
+            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, nullptr, target, gZ,
+                                         grad_pose ? acc : nullptr, loss, st),
+                    "fused adjoint kernel");
+    }
+    if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel");
+    return DUS_OK;
+}
+
+int dus_plan_step(dus_plan *p, const float *Z, const float *poses, const float *target, float *bmode,
+                  double *loss, float *grad_Z, float *grad_pose, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!p) return fail(DUS_EINVAL, "plan is NULL");
+    int s;
+    if ((s = check_ws(ws, ws_bytes, p->ws.total)) != DUS_OK) return s;
+    if (p->extent > 0) {
+        if (!Z || !poses || !target) return fail(DUS_EINVAL, "Z, poses and target are required");
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (p->flags & DUS_PLAN_NO_GRAPH) return plan_enqueue(p, Z, poses, target, bmode, loss, grad_Z, grad_pose, ws, st);
+    const void *key[9] = {Z, poses, target, bmode, loss, grad_Z, grad_pose, ws, nullptr};
+    bool same = p->exec != nullptr && p->key_ws_bytes == ws_bytes;
+    for (int i = 0; i < 8 && same; ++i) same = (key[i] == p->key[i]);
+    if (!same) {
+        plan_drop_graph(p);
+        DUS_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        s = plan_enqueue(p, Z, poses, target, bmode, loss, grad_Z, grad_pose, ws, p->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(p->cap, &g);
+        if (s != DUS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        p->graph = g;
+        e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            plan_drop_graph(p);
+            return hip_fail(e, "graph instantiate");
+        }
+        memcpy(p->key, key, sizeof(key));
+        p->key_ws_bytes = ws_bytes;
+    }
+    DUS_HIP(hipGraphLaunch(p->exec, st), "graph launch");
+    return DUS_OK;
+}
+
+void dus_plan_destroy(dus_plan *p)
+{
+    if (!p) return;
+    plan_drop_graph(p);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Internal launch records shared by the HIP kernels and the host ABI layer.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace dus {
+
+// Fans per launch: the fan table travels in the kernel arguments.
+constexpr int kMaxFans = 64;
+
+struct FanRec {
+    int32_t n_rays, n_samples;
+    float aperture, ds, r0;
+    int32_t speckle_id;
+    int64_t out_offset;     // element offset of the [n_rays][n_samples] image
+    int32_t ray_begin;      // first launch-wide ray index of this fan
+    int32_t blk_begin;      // first blur block of this fan
+    int32_t pose;           // row of the poses array
+    int32_t pivot_begin;    // pose-major index of this fan's first ray
+};
+static_assert(sizeof(FanRec) == 48, "FanRec layout");
+
+struct FanTable {
+    int32_t n;              // fans in this launch
+    int32_t total_rays;
+    int32_t total_blur_blocks;
+    int32_t pad_;
+    FanRec f[kMaxFans];
+};
+
+struct VolArgs {
+    const float *Z;
+    int32_t nx, ny, nz, pad_;
+    float h[3];
+    float o[3];
+};
+
+struct PhysArgs {
+    float alpha, freq;
+    int32_t refl, atten;
+    int32_t speckle, cell;
+    float Ar, gam, Ag0, Ag1;
+    int32_t blur;
+    float s0, s1;
+    uint32_t key0, key1;
+    int32_t blur_rmax;      // ceil(3 * max sigma), <= DUS_MAX_BLUR_RADIUS
+};
+
+// Per-pose accumulator of the adjoint: dL/dt (3) and dL/dR (9), FP64.
+constexpr int kPoseAcc = 12;
+
+// Launch wrappers (kernels.hip).  All enqueue on `st` and return the HIP
+// error of the launch.
+hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
+                          const FanTable &t, const float *poses, float *out,
+                          float *min_pivot, int pivot_base, hipStream_t st);
+hipError_t launch_backward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
+                           const FanTable &t, const float *poses, const float *gsrc,
+                           const float *target, float *gZ, double *pose_acc, double *loss,
+                           hipStream_t st);
+hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
+                       float *out, hipStream_t st);
+hipError_t launch_blur_residual(const PhysArgs &p, const FanTable &t, const float *pre,
+                                const float *target, float *image, float *resid, double *loss,
+                                hipStream_t st);
+hipError_t launch_pose_finalize(const double *acc, const float *poses, int n_poses,
+                                float *grad_pose, hipStream_t st);
+hipError_t launch_footprint(const VolArgs &v, const FanTable &t, const float *poses, uint8_t *mask,
+                            hipStream_t st);
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
+hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t st);
+hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
+                         hipStream_t st);
+hipError_t launch_pixel_gain(const PhysArgs &p, const FanRec &f, float *out, hipStream_t st);
+
+}  // namespace dus

@@ -1,0 +1,259 @@
+"""PyTorch front end of the fan-beam renderer.
+
+PyTorch provides device memory and streams; the renderer itself is the HIP
+library behind the C ABI (``_lib``).  ``Geometry`` packs the volume shape,
+the fans and the physics into the ABI's records once; ``render`` and
+``RenderBmode`` (a ``torch.autograd.Function`` with the hand-written adjoint)
+call the library on the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import DusFan, DusPhysics, DusSchedule, DusVolume, check
+
+
+def _stream() -> int:
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+@dataclass
+class Geometry:
+    """Volume shape + fans + physics as ABI records.
+
+    fans: sequence of objects with n_rays, n_samples, aperture, ds, r0 and
+    speckle_id attributes (``synth.FanSpec``).  Images of consecutive poses
+    are packed back to back: pose p starts at ``offsets[p]``.
+    """
+    shape: tuple                      # (nz, ny, nx)
+    spacing: tuple                    # (hx, hy, hz) mm
+    origin: tuple                     # (ox, oy, oz) mm
+    fans: list
+    phys: object                      # synth.PhysicsSpec-like
+    vol_c: DusVolume = field(init=False)
+    fans_c: ctypes.Array = field(init=False)
+    phys_c: DusPhysics = field(init=False)
+    offsets: np.ndarray = field(init=False)
+    total: int = field(init=False)
+
+    def __post_init__(self):
+        nz, ny, nx = self.shape
+        v = DusVolume()
+        v.nx, v.ny, v.nz = nx, ny, nz
+        v.spacing_mm = (ctypes.c_float * 3)(*[float(x) for x in self.spacing])
+        v.origin_mm = (ctypes.c_float * 3)(*[float(x) for x in self.origin])
+        self.vol_c = v
+        n = len(self.fans)
+        arr = (DusFan * max(n, 1))()
+        offs = np.zeros(n + 1, dtype=np.int64)
+        for i, f in enumerate(self.fans):
+            arr[i].n_rays = int(f.n_rays)
+            arr[i].n_samples = int(f.n_samples)
+            arr[i].aperture_rad = float(f.aperture)
+            arr[i].ds_mm = float(f.ds)
+            arr[i].r0_mm = float(f.r0)
+            arr[i].speckle_id = int(f.speckle_id)
+            arr[i].out_offset = int(offs[i])
+            offs[i + 1] = offs[i] + int(f.n_rays) * int(f.n_samples)
+        self.fans_c = arr
+        self.offsets = offs
+        self.total = int(offs[-1])
+        self.phys_c = physics_record(self.phys)
+
+    @property
+    def n_poses(self) -> int:
+        return len(self.fans)
+
+    @property
+    def total_rays(self) -> int:
+        return int(sum(int(f.n_rays) for f in self.fans))
+
+    def image(self, flat: torch.Tensor, p: int) -> torch.Tensor:
+        f = self.fans[p]
+        o = int(self.offsets[p])
+        return flat[o:o + int(f.n_rays) * int(f.n_samples)].view(int(f.n_rays), int(f.n_samples))
+
+    def workspace(self, with_backward: bool, device) -> torch.Tensor:
+        nb = check(_lib.lib().dus_workspace_bytes(ctypes.byref(self.vol_c), self.fans_c, self.n_poses,
+                                                 ctypes.byref(self.phys_c), int(with_backward)),
+                   "dus_workspace_bytes")
+        return torch.empty(max(int(nb), 1), dtype=torch.uint8, device=device)
+
+
+def physics_record(ph) -> DusPhysics:
+    p = DusPhysics()
+    p.alpha_db_cm_mhz = float(ph.alpha)
+    p.f_mhz = float(ph.freq)
+    p.refl_mode = int(ph.refl_mode)
+    p.atten_mode = int(ph.atten_mode)
+    p.speckle_on = int(bool(ph.speckle_on))
+    p.spk_cell = int(ph.spk_cell)
+    p.spk_Ar, p.spk_gamma = float(ph.Ar), float(ph.gamma)
+    p.spk_Ag0, p.spk_Ag1 = float(ph.Ag0), float(ph.Ag1)
+    p.blur_on = int(bool(ph.blur_on))
+    p.blur_sigma0, p.blur_sigma1 = float(ph.sigma0), float(ph.sigma1)
+    p.reserved = 0
+    p.seed = int(ph.seed) & 0xFFFFFFFFFFFFFFFF
+    return p
+
+
+def _check_inputs(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry):
+    if not Z.is_cuda or Z.dtype != torch.float32 or not Z.is_contiguous():
+        raise ValueError("Z must be a contiguous float32 CUDA tensor")
+    if tuple(Z.shape) != tuple(geom.shape):
+        raise ValueError(f"Z shape {tuple(Z.shape)} != geometry {tuple(geom.shape)}")
+    if (not poses.is_cuda or poses.dtype != torch.float32 or not poses.is_contiguous()
+            or tuple(poses.shape) != (geom.n_poses, 6)):
+        raise ValueError("poses must be a contiguous float32 CUDA tensor [n_poses, 6]")
+
+
+def render(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, want_pivot: bool = False,
+           out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Forward render; returns the packed image (and per-ray min pivots)."""
+    _check_inputs(Z, poses, geom)
+    dev = Z.device
+    if out is None:
+        out = torch.empty(max(geom.total, 1), dtype=torch.float32, device=dev)
+    piv = torch.empty(max(geom.total_rays, 1), dtype=torch.float32, device=dev) if want_pivot else None
+    if ws is None:
+        ws = geom.workspace(False, dev)
+    check(_lib.lib().dus_render_bmode(_ptr(Z), ctypes.byref(geom.vol_c), _ptr(poses), geom.fans_c,
+                                      geom.n_poses, ctypes.byref(geom.phys_c), _ptr(out), _ptr(piv),
+                                      _ptr(ws), ws.numel(), _stream()),
+          "dus_render_bmode")
+    out = out[:geom.total]
+    return (out, piv[:geom.total_rays]) if want_pivot else out
+
+
+def render_backward(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, grad_bmode: torch.Tensor,
+                    want_Z: bool = True, want_pose: bool = True, grad_Z: torch.Tensor | None = None,
+                    ws: torch.Tensor | None = None):
+    """Hand-written adjoint: (dL/dZ, dL/dpose) for dL/dbmode."""
+    _check_inputs(Z, poses, geom)
+    dev = Z.device
+    g = grad_bmode.contiguous().to(torch.float32)
+    if g.numel() < geom.total:
+        raise ValueError("grad_bmode too small")
+    gZ = None
+    if want_Z:
+        gZ = grad_Z if grad_Z is not None else torch.zeros_like(Z)
+    gp = torch.empty((geom.n_poses, 6), dtype=torch.float32, device=dev) if want_pose else None
+    if ws is None:
+        ws = geom.workspace(True, dev)
+    check(_lib.lib().dus_render_bmode_backward(_ptr(Z), ctypes.byref(geom.vol_c), _ptr(poses),
+                                               geom.fans_c, geom.n_poses, ctypes.byref(geom.phys_c),
+                                               _ptr(g), _ptr(gZ), _ptr(gp), _ptr(ws), ws.numel(),
+                                               _stream()),
+          "dus_render_bmode_backward")
+    return gZ, gp
+
+
+class RenderBmode(torch.autograd.Function):
+    """bmode = render(Z, poses); gradients from the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, Z, poses, geom):
+        ctx.geom = geom
+        ctx.save_for_backward(Z, poses)
+        return render(Z, poses, geom)
+
+    @staticmethod
+    def backward(ctx, grad):
+        Z, poses = ctx.saved_tensors
+        gZ, gp = render_backward(Z, poses, ctx.geom, grad, want_Z=ctx.needs_input_grad[0],
+                                 want_pose=ctx.needs_input_grad[1])
+        return gZ, gp, None
+
+
+def render_ad(Z, poses, geom):
+    return RenderBmode.apply(Z, poses, geom)
+
+
+def philox(counters: torch.Tensor, seed: int) -> torch.Tensor:
+    """Philox4x32-10 words (int32 view of uint32) for int32 counters [n, 4]."""
+    c = counters.contiguous()
+    out = torch.empty_like(c)
+    check(_lib.lib().dus_philox4x32_10(_ptr(c), c.shape[0], int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out),
+                                       _stream()), "dus_philox4x32_10")
+    return out
+
+
+def pixel_gain(fan, phys, device) -> torch.Tensor:
+    f = DusFan()
+    f.n_rays, f.n_samples = int(fan.n_rays), int(fan.n_samples)
+    f.aperture_rad, f.ds_mm, f.r0_mm = float(fan.aperture), float(fan.ds), float(fan.r0)
+    f.speckle_id, f.out_offset = int(fan.speckle_id), 0
+    out = torch.empty((max(f.n_rays, 1), max(f.n_samples, 1)), dtype=torch.float32, device=device)
+    pr = physics_record(phys)
+    check(_lib.lib().dus_pixel_gain(ctypes.byref(f), ctypes.byref(pr), _ptr(out), _stream()), "dus_pixel_gain")
+    return out[:f.n_rays, :f.n_samples]
+
+
+def footprint_voxels(poses: torch.Tensor, geom: Geometry) -> int:
+    """Number of distinct voxels in the union of all trilinear stencils."""
+    nz, ny, nx = geom.shape
+    mask = torch.zeros(nz * ny * nx, dtype=torch.uint8, device=poses.device)
+    check(_lib.lib().dus_footprint_mask(ctypes.byref(geom.vol_c), _ptr(poses), geom.fans_c, geom.n_poses,
+                                        _ptr(mask), _stream()), "dus_footprint_mask")
+    return int(mask.sum(dtype=torch.int64).item())
+
+
+class FusedStep:
+    """Batched fused forward + MSE + adjoint over all poses of ``geom``,
+    replayed from a captured HIP graph (``dus_plan``)."""
+
+    def __init__(self, geom: Geometry, pose_only: bool = False, zero_grad_z: bool = True,
+                 graph: bool = True, schedule: dict | None = None):
+        L = _lib.lib()
+        self.geom = geom
+        flags = (_lib.PLAN_POSE_ONLY if pose_only else 0) | (_lib.PLAN_ZERO_GRAD_Z if zero_grad_z else 0)
+        flags |= 0 if graph else _lib.PLAN_NO_GRAPH
+        h = ctypes.c_void_p()
+        check(L.dus_plan_create(ctypes.byref(h), ctypes.byref(geom.vol_c), geom.fans_c, geom.n_poses,
+                                ctypes.byref(geom.phys_c), flags), "dus_plan_create")
+        self._h = h
+        self._ws = None
+        if schedule:
+            self.set_schedule(**schedule)
+
+    def set_schedule(self, fwd_chunk=0, bwd_chunk=0, xcd_group=0):
+        s = DusSchedule(int(fwd_chunk), int(bwd_chunk), int(xcd_group), 0)
+        check(_lib.lib().dus_plan_set_schedule(self._h, ctypes.byref(s)), "dus_plan_set_schedule")
+
+    def get_schedule(self) -> dict:
+        s = DusSchedule()
+        check(_lib.lib().dus_plan_get_schedule(self._h, ctypes.byref(s)), "dus_plan_get_schedule")
+        return {"fwd_chunk": s.fwd_chunk, "bwd_chunk": s.bwd_chunk, "xcd_group": s.xcd_group}
+
+    def workspace(self, device) -> torch.Tensor:
+        if self._ws is None or self._ws.device != torch.device(device):
+            nb = check(_lib.lib().dus_plan_workspace_bytes(self._h), "dus_plan_workspace_bytes")
+            self._ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=device)
+        return self._ws
+
+    def step(self, Z, poses, target, bmode=None, loss=None, grad_Z=None, grad_pose=None):
+        _check_inputs(Z, poses, self.geom)
+        ws = self.workspace(Z.device)
+        check(_lib.lib().dus_plan_step(self._h, _ptr(Z), _ptr(poses), _ptr(target), _ptr(bmode), _ptr(loss),
+                                       _ptr(grad_Z), _ptr(grad_pose), _ptr(ws), ws.numel(), _stream()),
+              "dus_plan_step")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().dus_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

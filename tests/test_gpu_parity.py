@@ -1,0 +1,171 @@
+"""GPU parity: the HIP renderer (through the C ABI) against the FP64 oracle.
+
+Bars (fixed here, derived in the design doc):
+  forward images      per-image relative l2 <= 1e-5, and every pixel within
+                      1e-5 of the image's max |value|
+  adjoint             dL/dZ relative l2 <= 1e-5 over the volume; dL/dpose per
+                      component within 1e-5 * ||dL/dpose||
+  speckle generator   Philox words bit-exact
+"""
+import numpy as np
+import pytest
+
+from paper_2508_06768_amd import synth
+from tests import helpers as H
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+RTOL_IMG = 1e-5
+RTOL_GRAD = 1e-5
+
+
+def _gpu(case, geom=None):
+    from paper_2508_06768_amd.render import Geometry
+    geom = geom or Geometry(case.Z.shape, case.spacing, case.origin, case.fans, case.phys)
+    Z = torch.from_numpy(case.Z).to(DEV)
+    poses = torch.from_numpy(np.ascontiguousarray(case.poses, dtype=np.float32)).to(DEV)
+    return geom, Z, poses
+
+
+def ragged_case(refl=0, atten=0, effects=False, seed=7) -> synth.Case:
+    """48^3 brain-like volume; three tilted poses whose fans span several
+    tiles with ragged tails, a single-ray fan and a short fan."""
+    Z = synth.brain_volume(seed, 48, 1.0, semi_range=(3.0, 10.0))
+    rng = np.random.default_rng(seed)
+    poses = np.array([[23.5, 24.0, 0.0, 0.05, -0.04, 0.1],
+                      [20.0, 26.0, 1.5, -0.12, 0.08, -0.3],
+                      [25.0, 22.0, 0.5, 0.2, 0.1, 0.7]], dtype=np.float32)
+    fans = [synth.FanSpec(37, 1000, 1.1, 0.047, 0.3, 0),
+            synth.FanSpec(1, 777, 0.0, 0.061, 0.0, 1),
+            synth.FanSpec(65, 129, 1.4, 0.33, 1.0, 2)]
+    ph = synth.PhysicsSpec(refl_mode=refl, atten_mode=atten, speckle_on=effects, blur_on=effects,
+                           seed=int(rng.integers(1 << 40)), alpha=0.8, freq=4.0)
+    return synth.Case("ragged48", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans, ph)
+
+
+def _check_images(gpu, ref, tag):
+    rep = H.parity_report(gpu, ref)
+    print(tag, rep, flush=True)
+    assert rep["rel_l2"] <= RTOL_IMG, rep
+    assert rep["max_abs_over_max"] <= RTOL_IMG, rep
+
+
+# --------------------------------------------------------------------------
+def test_philox_bitexact():
+    from oracle import oracle as O
+    from paper_2508_06768_amd.render import philox
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    seed = 0x0123456789ABCDEF
+    out = philox(torch.from_numpy(ctr.view(np.int32)).to(DEV), seed).cpu().numpy().view(np.uint32)
+    ref = O.philox(ctr, [seed & 0xFFFFFFFF, seed >> 32])
+    np.testing.assert_array_equal(out, ref)
+
+
+@pytest.mark.parametrize("atten", [0, 1])
+def test_pixel_gain_matches_oracle(atten):
+    from oracle import oracle as O
+    from paper_2508_06768_amd.render import pixel_gain
+    fan = synth.FanSpec(5, 1037, 1.0, 0.21, 0.0, 9)
+    ph = synth.PhysicsSpec(speckle_on=True, atten_mode=atten, seed=12345, spk_cell=8)
+    g = pixel_gain(fan, ph, DEV).cpu().numpy()
+    of = H.oracle_fan(fan)
+    op = H.oracle_physics(ph)
+    ref = np.stack([O.speckle_ray(of, op, j) for j in range(5)])
+    if atten == 1:
+        k = np.arange(1037)
+        ref = ref * 10 ** (-2 * op.alpha * op.freq * (k * of.ds / 10) / 20)
+    np.testing.assert_allclose(g, ref, rtol=2e-6, atol=0)
+
+
+@pytest.mark.parametrize("refl,atten,effects", [(0, 0, False), (1, 0, False), (0, 1, True), (1, 2, True),
+                                                (0, 0, True)])
+def test_forward_parity_ragged(refl, atten, effects):
+    from paper_2508_06768_amd.render import render
+    case = ragged_case(refl, atten, effects)
+    geom, Z, poses = _gpu(case)
+    img, piv = render(Z, poses, geom, want_pivot=True)
+    ref, rpiv = H.oracle_render(case, want_pivot=True)
+    _check_images(img.cpu().numpy(), ref, f"ragged refl={refl} atten={atten} fx={effects}")
+    np.testing.assert_allclose(piv.cpu().numpy(), rpiv, rtol=1e-5)
+
+
+def test_forward_parity_phantom():
+    """64^3 phantom, 64 rays x 256 samples (near-pole rays included)."""
+    from paper_2508_06768_amd.render import render
+    case = synth.case_small_forward()
+    geom, Z, poses = _gpu(case)
+    img, piv = render(Z, poses, geom, want_pivot=True)
+    ref, rpiv = H.oracle_render(case, want_pivot=True)
+    _check_images(img.cpu().numpy(), ref, "phantom64")
+    np.testing.assert_allclose(piv.cpu().numpy(), rpiv, rtol=1e-5)
+
+
+def test_homogeneous_volume_is_exactly_silent():
+    from paper_2508_06768_amd.render import render
+    case = ragged_case(0, 0, True)
+    case.Z = np.full_like(case.Z, 1.61)
+    geom, Z, poses = _gpu(case)
+    img = render(Z, poses, geom).cpu().numpy()
+    assert np.all(img == 0.0)
+
+
+@pytest.mark.parametrize("refl,effects", [(0, False), (1, True), (0, True)])
+def test_backward_parity_ragged(refl, effects):
+    from paper_2508_06768_amd.render import render_backward
+    case = ragged_case(refl, 0, effects, seed=11)
+    geom, Z, poses = _gpu(case)
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(geom.total).astype(np.float32)
+    gZ, gp = render_backward(Z, poses, geom, torch.from_numpy(w).to(DEV))
+    rV, rp = H.oracle_backward(case, w.astype(np.float64))
+    gZ = gZ.cpu().numpy()
+    gp = gp.cpu().numpy()
+    e = H.rel_l2(gZ, rV)
+    print("dZ rel l2", e, flush=True)
+    assert e <= RTOL_GRAD
+    for p in range(len(case.fans)):
+        nrm = np.linalg.norm(rp[p])
+        print("pose", p, gp[p], rp[p], flush=True)
+        assert np.all(np.abs(gp[p] - rp[p]) <= RTOL_GRAD * nrm + 1e-30)
+
+
+def test_fused_plan_matches_oracle():
+    """dus_plan step (forward + MSE + adjoint in one captured graph)."""
+    from paper_2508_06768_amd.render import FusedStep
+    for effects in (False, True):
+        case = ragged_case(0, 0, effects, seed=21)
+        geom, Z, poses = _gpu(case)
+        tgt_poses = case.poses + np.float32([[0.6, -0.3, 0.2, 0.02, -0.03, 0.05]])
+        target = H.oracle_render(case, poses=tgt_poses)
+        T = torch.from_numpy(target.astype(np.float32)).to(DEV)
+        step = FusedStep(geom, zero_grad_z=True)
+        bm = torch.empty(geom.total, device=DEV)
+        loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+        gZ = torch.full_like(Z, 123.0)
+        gp = torch.empty((geom.n_poses, 6), device=DEV)
+        for _ in range(3):                      # replays of the same graph
+            step.step(Z, poses, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+        torch.cuda.synchronize()
+        img = H.oracle_render(case)
+        tf = target.astype(np.float32).astype(np.float64)
+        ref_loss = 0.0
+        grad = np.zeros_like(img)
+        off = 0
+        for f in case.fans:
+            n = f.n_rays * f.n_samples
+            d = img[off:off + n] - tf[off:off + n]
+            ref_loss += np.mean(d * d)
+            grad[off:off + n] = 2 * d / n
+            off += n
+        rV, rp = H.oracle_backward(case, grad)
+        _check_images(bm.cpu().numpy(), img, f"plan image fx={effects}")
+        assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
+        e = H.rel_l2(gZ.cpu().numpy(), rV)
+        print("plan dZ rel l2", e, flush=True)
+        assert e <= RTOL_GRAD
+        gpn = gp.cpu().numpy()
+        for p in range(len(case.fans)):
+            assert np.all(np.abs(gpn[p] - rp[p]) <= RTOL_GRAD * np.linalg.norm(rp[p]) + 1e-30)
