@@ -193,6 +193,11 @@ typedef struct {
     int32_t reserved;
 } dus_schedule;
 
+/* Process-wide schedule used by dus_render_bmode / dus_render_bmode_backward
+ * (plans carry their own).  Not thread-safe against concurrent render calls. */
+int dus_set_schedule(const dus_schedule *sched);
+int dus_get_schedule(dus_schedule *sched);
+
 int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans,
                     int32_t n_poses, const dus_physics *phys, int32_t flags);
 int64_t dus_plan_workspace_bytes(const dus_plan *plan);

@@ -60,6 +60,8 @@ SIGNATURES = {
     "dus_pixel_gain": (ctypes.c_int, [ctypes.POINTER(DusFan), ctypes.POINTER(DusPhysics), c_vp, c_vp]),
     "dus_footprint_mask": (ctypes.c_int, [ctypes.POINTER(DusVolume), c_vp, ctypes.POINTER(DusFan), c_i32,
                                           c_vp, c_vp]),
+    "dus_set_schedule": (ctypes.c_int, [ctypes.POINTER(DusSchedule)]),
+    "dus_get_schedule": (ctypes.c_int, [ctypes.POINTER(DusSchedule)]),
     "dus_plan_create": (ctypes.c_int, [ctypes.POINTER(c_vp), ctypes.POINTER(DusVolume), ctypes.POINTER(DusFan),
                                        c_i32, ctypes.POINTER(DusPhysics), c_i32]),
     "dus_plan_workspace_bytes": (c_i64, [c_vp]),

@@ -38,7 +38,7 @@ int hip_fail(hipError_t e, const char *where)
 bool finite_f(float x) { return isfinite(x) != 0; }
 
 constexpr int kDefaultFwdChunk = 8;
-constexpr int kDefaultBwdChunk = 8;
+constexpr int kDefaultBwdChunk = 4;
 constexpr int kDefaultXcdGroup = 16;
 
 int check_volume(const dus_volume *v)
@@ -201,6 +201,7 @@ struct WsLayout {
     size_t eb = 0, eb_bytes = 0;       // blur-transposed dL/dI (adjoint with blur)
     size_t res = 0, res_bytes = 0;     // MSE residual (plan with blur)
     size_t acc = 0, acc_bytes = 0;     // pose accumulators
+    size_t zb = 0, zb_bytes = 0;       // dL/dZ per sample (adjoint)
     size_t total = 0;
 };
 
@@ -226,6 +227,9 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         off = align_up(off + img);
     }
     if (mode == 1 || mode == 2) {
+        L.zb = off;
+        L.zb_bytes = img;
+        off = align_up(off + img);
         L.acc = off;
         L.acc_bytes = (size_t)std::max(n_poses, 1) * dus::kPoseAcc * sizeof(double);
         off = align_up(off + L.acc_bytes);
@@ -263,6 +267,19 @@ struct Sched {
     int bwd_chunk = kDefaultBwdChunk;
     int xcd_group = kDefaultXcdGroup;
 };
+
+Sched g_sched;     // schedule of the direct (non-plan) calls
+
+int make_sched(const dus_schedule *sc, Sched &n)
+{
+    n.fwd_chunk = sc->fwd_chunk ? sc->fwd_chunk : kDefaultFwdChunk;
+    n.bwd_chunk = sc->bwd_chunk ? sc->bwd_chunk : kDefaultBwdChunk;
+    n.xcd_group = sc->xcd_group ? sc->xcd_group : kDefaultXcdGroup;
+    if (n.fwd_chunk != 4 && n.fwd_chunk != 8 && n.fwd_chunk != 16) return fail(DUS_EINVAL, "fwd_chunk must be 4, 8 or 16");
+    if (n.bwd_chunk != 4 && n.bwd_chunk != 8) return fail(DUS_EINVAL, "bwd_chunk must be 4 or 8");
+    if (n.xcd_group < 1 || n.xcd_group > 64) return fail(DUS_EINVAL, "xcd_group must be in [1, 64]");
+    return DUS_OK;
+}
 
 int enqueue_forward(const Sched &sc, const dus::VolArgs &va, const dus::PhysArgs &pa,
                     const std::vector<dus::FanTable> &tabs, const float *poses, float *out,
@@ -337,7 +354,7 @@ int dus_render_bmode(const float *Z, const dus_volume *vol, const float *poses, 
     const auto tabs = build_tables(fans, n_poses);
     const dus::VolArgs va = vol_args(Z, vol);
     const dus::PhysArgs pa = phys_args(phys);
-    Sched sc;
+    const Sched sc = g_sched;
     float *dst = phys->blur_on ? reinterpret_cast<float *>((char *)ws + L.pre) : bmode;
     if ((s = enqueue_forward(sc, va, pa, tabs, poses, dst, ray_min_pivot, st)) != DUS_OK) return s;
     if (phys->blur_on)
@@ -364,7 +381,7 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
         const auto tabs = build_tables(fans, n_poses);
         const dus::VolArgs va = vol_args(Z, vol);
         const dus::PhysArgs pa = phys_args(phys);
-        Sched sc;
+        const Sched sc = g_sched;
         const float *src = grad_bmode;
         if (phys->blur_on) {
             float *eb = reinterpret_cast<float *>((char *)ws + L.eb);
@@ -372,7 +389,8 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
             src = eb;
         }
         for (const auto &t : tabs)
-            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, src, nullptr, grad_Z,
+            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, src, nullptr,
+                                         reinterpret_cast<float *>((char *)ws + L.zb), grad_Z,
                                          grad_pose ? acc : nullptr, nullptr, st),
                     "adjoint kernel launch");
     }
@@ -477,15 +495,30 @@ int dus_plan_set_schedule(dus_plan *p, const dus_schedule *sc)
 {
     if (!p || !sc) return fail(DUS_EINVAL, "NULL pointer");
     Sched n;
-    n.fwd_chunk = sc->fwd_chunk ? sc->fwd_chunk : kDefaultFwdChunk;
-    n.bwd_chunk = sc->bwd_chunk ? sc->bwd_chunk : kDefaultBwdChunk;
-    n.xcd_group = sc->xcd_group ? sc->xcd_group : kDefaultXcdGroup;
-    if (n.fwd_chunk != 4 && n.fwd_chunk != 8 && n.fwd_chunk != 16) return fail(DUS_EINVAL, "fwd_chunk must be 4, 8 or 16");
-    if (n.bwd_chunk != 4 && n.bwd_chunk != 8) return fail(DUS_EINVAL, "bwd_chunk must be 4 or 8");
-    if (n.xcd_group < 1 || n.xcd_group > 64) return fail(DUS_EINVAL, "xcd_group must be in [1, 64]");
-    // the adjoint keeps one carry per tile in LDS: S <= 16384 for either chunk
+    int s;
+    if ((s = make_sched(sc, n)) != DUS_OK) return s;
     p->sched = n;
     plan_drop_graph(p);
+    return DUS_OK;
+}
+
+int dus_set_schedule(const dus_schedule *sc)
+{
+    if (!sc) return fail(DUS_EINVAL, "NULL pointer");
+    Sched n;
+    int s;
+    if ((s = make_sched(sc, n)) != DUS_OK) return s;
+    g_sched = n;
+    return DUS_OK;
+}
+
+int dus_get_schedule(dus_schedule *sc)
+{
+    if (!sc) return fail(DUS_EINVAL, "NULL pointer");
+    sc->fwd_chunk = g_sched.fwd_chunk;
+    sc->bwd_chunk = g_sched.bwd_chunk;
+    sc->xcd_group = g_sched.xcd_group;
+    sc->reserved = 0;
     return DUS_OK;
 }
 
@@ -506,6 +539,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     const dus::PhysArgs pa = phys_args(&p->phys);
     const int n_poses = (int)p->fans.size();
     double *acc = reinterpret_cast<double *>((char *)ws + p->ws.acc);
+    float *zbar = reinterpret_cast<float *>((char *)ws + p->ws.zb);
     float *gZ = (p->flags & DUS_PLAN_POSE_ONLY) ? nullptr : grad_Z;
     if (grad_pose) DUS_HIP(dus::launch_zero_f64(acc, (int64_t)n_poses * dus::kPoseAcc, st), "zero kernel");
     if (loss) DUS_HIP(dus::launch_zero_f64(loss, 1, st), "zero kernel");
@@ -523,7 +557,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         for (const auto &t : p->tabs) DUS_HIP(dus::launch_blur(true, pa, t, res, eb, st), "blur^T kernel");
         if (gZ || grad_pose)
             for (const auto &t : p->tabs)
-                DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, nullptr, gZ,
+                DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, nullptr, zbar, gZ,
                                              grad_pose ? acc : nullptr, nullptr, st),
                         "adjoint kernel");
     } else {
@@ -532,7 +566,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
             if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st)) != DUS_OK) return s;
         }
         for (const auto &t : p->tabs)
-            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, nullptr, target, gZ,
+            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, nullptr, target, zbar, gZ,
                                          grad_pose ? acc : nullptr, loss, st),
                     "fused adjoint kernel");
     }

@@ -55,10 +55,11 @@ constexpr int kPoseAcc = 12;
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out,
                           float *min_pivot, int pivot_base, hipStream_t st);
+// adjoint: dL/dZ per sample into zbar (image layout), then its scatter
 hipError_t launch_backward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                            const FanTable &t, const float *poses, const float *gsrc,
-                           const float *target, float *gZ, double *pose_acc, double *loss,
-                           hipStream_t st);
+                           const float *target, float *zbar, float *gZ, double *pose_acc,
+                           double *loss, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st);
 hipError_t launch_blur_residual(const PhysArgs &p, const FanTable &t, const float *pre,

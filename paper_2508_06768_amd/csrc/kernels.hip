@@ -578,8 +578,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                                                  const float *__restrict__ poses,
                                                  const float *__restrict__ gsrc,
                                                  const float *__restrict__ target,
-                                                 float *__restrict__ gZ,
-                                                 double *__restrict__ pose_acc,
+                                                 float *__restrict__ zbar,
                                                  double *__restrict__ loss_acc, int xgrp)
 {
     constexpr int T = 64 * C;
@@ -609,8 +608,6 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     const long long obase = fr.out_offset + (long long)j * S;
     const int ntiles = (S + T - 1) / T;
     const double inv_npix = 1.0 / ((double)fr.n_rays * (double)S);
-    const int sxy = v.nx * v.ny;
-    const double ih[3] = {1.0 / (double)v.h[0], 1.0 / (double)v.h[1], 1.0 / (double)v.h[2]};
 
     // forward sweep: state at every tile start
     {
@@ -647,7 +644,6 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     Adj lam{0.0, 0.0, 0.0};        // adjoint of the state at the current tile's end
     double rbar_next = 0.0;        // rho-bar of the interface just after this tile
     double z_next = 0.0;           // first sample of the next tile
-    double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
     double loss = 0.0;
     for (int t = ntiles - 1; t >= 0; --t) {
         const int t0 = t * T;
@@ -679,7 +675,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         chunk_product<C>(s_rho, base, t0, S, a2, sgn, Q, qd);
         scan_exclusive(lane, Q, qd, X, xd, Tot, td);
         // forward walk: states before each step
-        double sv0[C], sv1[C], sD[C], seb[C];
+        double sv0[C], sv1[C], sD[C];
         {
             double v0 = fma(c0, X.a, c1 * X.c);
             double v1 = fma(c0, X.b, c1 * X.d);
@@ -691,7 +687,6 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                 sv0[i] = v0;
                 sv1[i] = v1;
                 sD[i] = D;
-                double eb = 0.0;
                 if (valid) {
                     const double r = s_rho[pad8(base + i)];
                     const Map m = make_map(r, a2, sgn, true);
@@ -701,9 +696,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                         const double gn = s_gain[pad4(base + i)];
                         const double diff = e * gn - (double)s_eb[pad4(base + i)];
                         loss += diff * diff * inv_npix;
-                        eb = 2.0 * diff * inv_npix * gn;
-                    } else {
-                        eb = s_eb[pad4(base + i)];
+                        s_eb[pad4(base + i)] = (float)(2.0 * diff * inv_npix * gn);
                     }
                     const double v0n = fma(v0, m.m00, v1 * m.m10);
                     v0 = v0n;
@@ -713,7 +706,6 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                     const double diff = -(double)s_eb[pad4(base + i)];
                     loss += diff * diff * inv_npix;
                 }
-                seb[i] = eb;
             }
         }
         // chunk's affine map: lambda_start = lambda_end J + f (f from lambda_end = 0)
@@ -723,7 +715,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             const int k = t0 + base + i;
             if (k >= 1 && k < S) {
                 double rb;
-                f = adj_step(f, sv0[i], sv1[i], sD[i], s_rho[pad8(base + i)], a2, sgn, seb[i], rb);
+                f = adj_step(f, sv0[i], sv1[i], sD[i], s_rho[pad8(base + i)], a2, sgn, s_eb[pad4(base + i)], rb);
             }
         }
         // suffix composition over lanes: Psi_l = Phi_l o Phi_{l+1} o ... o Phi_63
@@ -776,7 +768,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             const int k = t0 + base + i;
             double rb = 0.0;
             if (k >= 1 && k < S)
-                le = adj_step(le, sv0[i], sv1[i], sD[i], s_rho[pad8(base + i)], a2, sgn, seb[i], rb);
+                le = adj_step(le, sv0[i], sv1[i], sD[i], s_rho[pad8(base + i)], a2, sgn, s_eb[pad4(base + i)], rb);
             s_rho[pad8(base + i)] = rb;       // s_rho now holds rho-bar
         }
         // adjoint of this tile's start state, expressed for the previous tile's
@@ -790,18 +782,18 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         }
         __syncthreads();
 
-        // dL/dZ_k per sample, scatter into the volume gradient and the pose sums
+        // dL/dZ_k per sample (rho depends on the samples on both sides)
 #pragma unroll
         for (int jj = 0; jj < C; ++jj) {
             const int i = jj * 64 + lane;
             const int k = t0 + i;
             if (k >= S) continue;
+            double zb = 0.0;
             const double zk = s_z[pad8(i)];
             const double zl = (i > 0) ? s_z[pad8(i - 1)] : zstart;
             const double zr = (i + 1 < T) ? s_z[pad8(i + 1)] : z_next;
             const double rl = (k >= 1) ? s_rho[pad8(i)] : 0.0;                      // interface k-1
             const double rr = (k + 1 < S) ? ((i + 1 < T) ? s_rho[pad8(i + 1)] : rbar_next) : 0.0;
-            double zb = 0.0;
             if (rl != 0.0) {
                 // rho(zl, zk): d/dzk = sgn(zk - zl)^abs * 2 zl / (zl + zk)^2
                 const double s = zl + zk;
@@ -816,8 +808,85 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                 if (absm) dz *= (zr > zk) ? 1.0 : ((zr < zk) ? -1.0 : 0.0);
                 zb = fma(rr, dz, zb);
             }
-            if (zb == 0.0) continue;
-            const Stencil st = stencil_at(v, ray, k);
+            zbar[obase + k] = (float)zb;
+        }
+        rbar_next = lane_read(s_rho[pad8(lane)], 0);
+        z_next = lane_read(s_z[pad8(lane)], 0);
+        __syncthreads();
+    }
+    if (FUSED && loss_acc) {
+        const double ls = wave_sum(loss);
+        if (lane == 0) atomicAdd(loss_acc, ls);
+    }
+}
+
+// --------------------------------------------------------------------------
+// scatter of dL/dZ_k: trilinear weights into the volume gradient, and the
+// pose sums.  A workgroup takes RB neighbouring rays of one fan and walks
+// them together in groups of 64 depths.  The stencils of such a group fill a
+// small box of the volume (neighbouring rays of a fan overlap), so the group
+// accumulates into an LDS copy of that box with LDS atomics and then flushes
+// the box row by row: one global atomic per touched voxel, consecutive lanes
+// on consecutive x.  A group whose box does not fit falls back to per-sample
+// global atomics.
+// --------------------------------------------------------------------------
+constexpr int kBoxCap = 4096;      // floats of LDS box per workgroup
+
+__device__ __forceinline__ int wave_min_i(int x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d));
+    return x;
+}
+
+__device__ __forceinline__ int wave_max_i(int x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d));
+    return x;
+}
+
+template <int RB>
+__global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, const float *__restrict__ poses,
+                                                     const float *__restrict__ zbar, float *__restrict__ gZ,
+                                                     double *__restrict__ pose_acc, int xgrp)
+{
+    __shared__ float s_box[kBoxCap];
+    __shared__ int s_bb[RB][6];
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, lane = tid & 63;
+    // block -> (fan, first ray); each fan owns ceil(n_rays / RB) blocks
+    const int b = remap_block(blockIdx.x, gridDim.x, xgrp);
+    int fi = 0, acc = 0;
+    for (;; ++fi) {
+        const int nb = (tab.f[fi].n_rays + RB - 1) / RB;
+        if (b < acc + nb || fi + 1 == tab.n) break;
+        acc += nb;
+    }
+    const FanRec fr = tab.f[fi];
+    const int j = (b - acc) * RB + w;
+    const bool ray_ok = j < fr.n_rays;
+    const int S = fr.n_samples;
+    PhysArgs p{};
+    p.atten = 2;
+    Ray ray;
+    setup_ray(v, p, fr, poses, ray_ok ? j : 0, ray);
+    const long long obase = fr.out_offset + (long long)j * S;
+    const int sxy = v.nx * v.ny;
+    const double ih[3] = {1.0 / (double)v.h[0], 1.0 / (double)v.h[1], 1.0 / (double)v.h[2]};
+    double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < S; k0 += 64) {
+        const int k = k0 + lane;
+        const float zbf = (ray_ok && k < S) ? zbar[obase + k] : 0.0f;
+        const bool act = (zbf != 0.0f);
+        Stencil st{0, 0.0, 0.0, 0.0};
+        int ix = 0, iy = 0, iz = 0;
+        if (act) {
+            st = stencil_at(v, ray, k);
+            iz = st.idx / sxy;
+            const int rem = st.idx - iz * sxy;
+            iy = rem / v.nx;
+            ix = rem - iy * v.nx;
             if (pose_acc) {
                 double gu[3];
                 trilinear(v.Z, v.nx, sxy, st, gu);
@@ -826,6 +895,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                                      fma(kk, ray.du[2], ray.u0[2])};
                 const int n[3] = {v.nx, v.ny, v.nz};
                 const double sk = fma(kk, ray.ds, ray.r0);
+                const double zb = (double)zbf;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const bool inside = (u[a] >= 0.0) && (u[a] <= (double)(n[a] - 1));
@@ -834,26 +904,74 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                     gssum[a] = fma(sk, gp, gssum[a]);
                 }
             }
-            if (gZ) {
-                const float zbf = (float)zb;
-                const float fx = (float)st.fx, fy = (float)st.fy, fz = (float)st.fz;
-                const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
-                float *q = gZ + st.idx;
-                atomicAdd(q, zbf * gx * gy * gz);
-                atomicAdd(q + 1, zbf * fx * gy * gz);
-                atomicAdd(q + v.nx, zbf * gx * fy * gz);
-                atomicAdd(q + v.nx + 1, zbf * fx * fy * gz);
-                atomicAdd(q + sxy, zbf * gx * gy * fz);
-                atomicAdd(q + sxy + 1, zbf * fx * gy * fz);
-                atomicAdd(q + sxy + v.nx, zbf * gx * fy * fz);
-                atomicAdd(q + sxy + v.nx + 1, zbf * fx * fy * fz);
+        }
+        if (!gZ) continue;     // uniform over the block
+        // bounding box of the group's stencil cells
+        {
+            const int big = 0x3fffffff;
+            const int mnx = wave_min_i(act ? ix : big), mny = wave_min_i(act ? iy : big);
+            const int mnz = wave_min_i(act ? iz : big);
+            const int mxx = wave_max_i(act ? ix : -1), mxy = wave_max_i(act ? iy : -1);
+            const int mxz = wave_max_i(act ? iz : -1);
+            if (lane == 0) {
+                s_bb[w][0] = mnx; s_bb[w][1] = mny; s_bb[w][2] = mnz;
+                s_bb[w][3] = mxx; s_bb[w][4] = mxy; s_bb[w][5] = mxz;
             }
         }
-        rbar_next = lane_read(s_rho[pad8(lane)], 0);
-        z_next = lane_read(s_z[pad8(lane)], 0);
+        __syncthreads();
+        int ox = s_bb[0][0], oy = s_bb[0][1], oz = s_bb[0][2];
+        int ex = s_bb[0][3], ey = s_bb[0][4], ez = s_bb[0][5];
+#pragma unroll
+        for (int q = 1; q < RB; ++q) {
+            ox = min(ox, s_bb[q][0]); oy = min(oy, s_bb[q][1]); oz = min(oz, s_bb[q][2]);
+            ex = max(ex, s_bb[q][3]); ey = max(ey, s_bb[q][4]); ez = max(ez, s_bb[q][5]);
+        }
+        __syncthreads();
+        if (ex < 0) continue;  // nothing to scatter in this group (uniform)
+        const int bx = ex - ox + 2, by = ey - oy + 2, bz = ez - oz + 2;
+        int rw = 1;
+        while (rw < bx) rw <<= 1;
+        const bool fits = (long long)rw * by * bz <= kBoxCap;
+        const float fx = (float)st.fx, fy = (float)st.fy, fz = (float)st.fz;
+        const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+        const float wc[8] = {zbf * gx * gy * gz, zbf * fx * gy * gz, zbf * gx * fy * gz, zbf * fx * fy * gz,
+                             zbf * gx * gy * fz, zbf * fx * gy * fz, zbf * gx * fy * fz, zbf * fx * fy * fz};
+        if (!fits) {
+            if (act) {
+                const int off[8] = {0, 1, v.nx, v.nx + 1, sxy, sxy + 1, sxy + v.nx, sxy + v.nx + 1};
+                float *q = gZ + st.idx;
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (wc[c] != 0.0f) atomicAdd(q + off[c], wc[c]);
+            }
+            continue;
+        }
+        const int plane = rw * by;
+        const int nbox = plane * bz;
+        for (int t = tid; t < nbox; t += 64 * RB) s_box[t] = 0.0f;
+        __syncthreads();
+        if (act) {
+            const int l = ((iz - oz) * by + (iy - oy)) * rw + (ix - ox);
+            const int off[8] = {0, 1, rw, rw + 1, plane, plane + 1, plane + rw, plane + rw + 1};
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (wc[c] != 0.0f) atomicAdd(&s_box[l + off[c]], wc[c]);
+        }
+        __syncthreads();
+        int lg2 = 0;
+        while ((1 << lg2) < rw) ++lg2;
+        for (int t = tid; t < nbox; t += 64 * RB) {
+            const float val = s_box[t];
+            if (val != 0.0f) {
+                const int lx = t & (rw - 1);
+                const int row = t >> lg2;
+                const int lz = row / by, ly = row - lz * by;
+                atomicAdd(gZ + ((oz + lz) * v.ny + (oy + ly)) * v.nx + (ox + lx), val);
+            }
+        }
         __syncthreads();
     }
-    if (pose_acc) {
+    if (pose_acc && ray_ok) {
         double r[6];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -861,19 +979,15 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             r[3 + a] = wave_sum(gssum[a]);
         }
         if (lane == 0) {
-            double *acc = pose_acc + (size_t)kPoseAcc * fr.pose;
+            double *pa = pose_acc + (size_t)kPoseAcc * fr.pose;
             // dL/dt = sum g;  dL/dR = sum g (s dir)^T, dir = (sx, 0, cz)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                atomicAdd(acc + a, r[a]);
-                atomicAdd(acc + 3 + 3 * a + 0, r[3 + a] * ray.dirx);
-                atomicAdd(acc + 3 + 3 * a + 2, r[3 + a] * ray.dirz);
+                atomicAdd(pa + a, r[a]);
+                atomicAdd(pa + 3 + 3 * a + 0, r[3 + a] * ray.dirx);
+                atomicAdd(pa + 3 + 3 * a + 2, r[3 + a] * ray.dirz);
             }
         }
-    }
-    if (FUSED && loss_acc) {
-        const double ls = wave_sum(loss);
-        if (lane == 0) atomicAdd(loss_acc, ls);
     }
 }
 
@@ -1162,7 +1276,7 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 #define DUS_BWD_LAUNCH(CH, SPK, FUSED)                                                          \
     hipLaunchKernelGGL((k_backward<CH, SPK, FUSED>), dim3(grid), dim3(64), 0, st, v, p, t,      \
-                       poses, gsrc, target, gZ, pose_acc, loss, xcd_group)
+                       poses, gsrc, target, zbar, loss, xcd_group)
 
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
@@ -1177,8 +1291,8 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 hipError_t launch_backward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                            const FanTable &t, const float *poses, const float *gsrc,
-                           const float *target, float *gZ, double *pose_acc, double *loss,
-                           hipStream_t st)
+                           const float *target, float *zbar, float *gZ, double *pose_acc,
+                           double *loss, hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
@@ -1189,6 +1303,13 @@ hipError_t launch_backward(int chunk, int xcd_group, const VolArgs &v, const Phy
     default:
         return hipErrorInvalidValue;
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || (!gZ && !pose_acc)) return e;
+    constexpr int RB = 4;
+    int blocks = 0;
+    for (int f = 0; f < t.n; ++f) blocks += (t.f[f].n_rays + RB - 1) / RB;
+    hipLaunchKernelGGL((k_scatter<RB>), dim3(blocks), dim3(64 * RB), 0, st, v, t, poses, zbar, gZ, pose_acc,
+                       xcd_group);
     return hipGetLastError();
 }
 

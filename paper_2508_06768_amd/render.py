@@ -198,6 +198,18 @@ def pixel_gain(fan, phys, device) -> torch.Tensor:
     return out[:f.n_rays, :f.n_samples]
 
 
+def set_schedule(fwd_chunk=0, bwd_chunk=0, xcd_group=0):
+    """Schedule of the direct render / adjoint calls (0 = library default)."""
+    s = DusSchedule(int(fwd_chunk), int(bwd_chunk), int(xcd_group), 0)
+    check(_lib.lib().dus_set_schedule(ctypes.byref(s)), "dus_set_schedule")
+
+
+def get_schedule() -> dict:
+    s = DusSchedule()
+    check(_lib.lib().dus_get_schedule(ctypes.byref(s)), "dus_get_schedule")
+    return {"fwd_chunk": s.fwd_chunk, "bwd_chunk": s.bwd_chunk, "xcd_group": s.xcd_group}
+
+
 def footprint_voxels(poses: torch.Tensor, geom: Geometry) -> int:
     """Number of distinct voxels in the union of all trilinear stencils."""
     nz, ny, nx = geom.shape

@@ -45,6 +45,16 @@ def ragged_case(refl=0, atten=0, effects=False, seed=7) -> synth.Case:
     return synth.Case("ragged48", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans, ph)
 
 
+def coarse_case(seed=5) -> synth.Case:
+    """Coarse depth steps (1.2 voxel per sample): the 64-sample groups do not
+    fit the adjoint's LDS box and take the per-sample atomic path."""
+    Z = synth.brain_volume(seed, 40, 1.0, semi_range=(3.0, 9.0))
+    poses = np.array([[19.5, 18.0, 0.0, 0.3, -0.2, 0.1]], dtype=np.float32)
+    fans = [synth.FanSpec(9, 100, 0.6, 1.2, 0.0, 0)]
+    ph = synth.PhysicsSpec(seed=seed, speckle_on=True)
+    return synth.Case("coarse40", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans, ph)
+
+
 def _check_images(gpu, ref, tag):
     rep = H.parity_report(gpu, ref)
     print(tag, rep, flush=True)
@@ -112,10 +122,10 @@ def test_homogeneous_volume_is_exactly_silent():
     assert np.all(img == 0.0)
 
 
-@pytest.mark.parametrize("refl,effects", [(0, False), (1, True), (0, True)])
+@pytest.mark.parametrize("refl,effects", [(0, False), (1, True), (0, True), ("coarse", None)])
 def test_backward_parity_ragged(refl, effects):
     from paper_2508_06768_amd.render import render_backward
-    case = ragged_case(refl, 0, effects, seed=11)
+    case = coarse_case() if refl == "coarse" else ragged_case(refl, 0, effects, seed=11)
     geom, Z, poses = _gpu(case)
     rng = np.random.default_rng(3)
     w = rng.standard_normal(geom.total).astype(np.float32)

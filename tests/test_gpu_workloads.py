@@ -1,0 +1,200 @@
+"""GPU checks at the benchmark's full sizes and on the edge cases.
+
+* the 512 x 1024 adjoint workload: GPU gradients against the FP64 oracle's
+  adjoint (rel. 1e-5) and against FP64 central finite differences of the
+  oracle's forward (64 footprint voxels, 8 voxels outside it, all 6 pose
+  parameters) within 1e-3;
+* the uneven 64-pose batch: batched launch == one pose per launch, and
+  sampled poses against the oracle;
+* every schedule gives the same result; graph replays agree;
+* maximum sample count, single ray, single sample, empty fans, 2-voxel axes.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_06768_amd import synth
+from tests import helpers as H
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _gpu(case, fans=None, poses=None):
+    from paper_2508_06768_amd.render import Geometry
+    fans = case.fans if fans is None else fans
+    poses = case.poses if poses is None else poses
+    geom = Geometry(case.Z.shape, case.spacing, case.origin, fans, case.phys)
+    return (geom, torch.from_numpy(case.Z).to(DEV),
+            torch.from_numpy(np.ascontiguousarray(poses, dtype=np.float32)).to(DEV))
+
+
+def test_adjoint_full_size_vs_oracle_and_finite_differences():
+    from paper_2508_06768_amd.render import render, render_backward
+    case = synth.case_adjoint()
+    geom, Z, P = _gpu(case)
+    print("case", case.name, "rays", case.fans[0].n_rays, "samples", case.fans[0].n_samples, flush=True)
+    target = H.oracle_render(case, poses=case.extra["target_poses"])
+    tf = target.astype(np.float32).astype(np.float64)
+    img = render(Z, P, geom)
+    ref = H.oracle_render(case)
+    rep = H.parity_report(img.cpu().numpy(), ref)
+    print("forward", rep, flush=True)
+    assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
+    # MSE gradient of the GPU image, adjoint on the GPU
+    n = ref.size
+    gimg = 2.0 * (img.double() - torch.from_numpy(tf).to(DEV)) / n
+    gZ, gp = render_backward(Z, P, geom, gimg.float())
+    gZ = gZ.cpu().numpy().astype(np.float64)
+    gp = gp.cpu().numpy()[0].astype(np.float64)
+    # FP64 oracle adjoint with its own image
+    _, g_or = O.mse_loss_grad(ref, tf)
+    rV, rp = H.oracle_backward(case, g_or)
+    e = H.rel_l2(gZ, rV)
+    print("dZ vs oracle adjoint", e, "pose", gp, rp[0], flush=True)
+    assert e <= 1e-5
+    assert np.all(np.abs(gp - rp[0]) <= 1e-5 * np.linalg.norm(rp[0]))
+    # finite differences of the oracle's forward
+    vol = H.oracle_volume(case)
+    fan = H.oracle_fan(case.fans[0])
+    ph = H.oracle_physics(case.phys)
+    pose = case.poses[0].astype(np.float64)
+    rng = np.random.default_rng(1003)
+    flat = np.abs(rV.reshape(-1))
+    hot = np.flatnonzero(flat > 1e-2 * flat.max())
+    idx = list(rng.choice(hot, size=64, replace=False))
+    cold = np.flatnonzero(flat == 0.0)
+    idx_cold = list(rng.choice(cold, size=8, replace=False))
+    fd = O.fd_voxels(vol, pose, fan, ph, tf, idx + idx_cold, h=1e-6)
+    g_sel = gZ.reshape(-1)[idx + idx_cold]
+    err = np.abs(g_sel[:64] - fd[:64]) / np.abs(fd[:64])
+    print("voxel FD rel err max", err.max(), "median", np.median(err), flush=True)
+    assert np.all(g_sel[64:] == 0.0)
+    assert np.all(fd[64:] == 0.0)
+    assert np.linalg.norm(g_sel[:64] - fd[:64]) <= 1e-3 * np.linalg.norm(fd[:64])
+    assert np.all(err <= 1e-2)
+    fdp = O.fd_pose(vol, pose, fan, ph, tf, h_t=1e-4, h_w=1e-6)
+    print("pose FD", fdp, "gpu", gp, flush=True)
+    assert np.linalg.norm(gp - fdp) <= 1e-3 * np.linalg.norm(fdp)
+
+
+def test_batched_equals_plain_and_oracle():
+    """The uneven 64-pose batch in one launch equals one pose per launch, and
+    sampled poses (the longest, the widest, two others) match the oracle."""
+    from paper_2508_06768_amd.render import Geometry, render, render_backward
+    case = synth.case_batched()
+    geom, Z, P = _gpu(case)
+    print("case", case.name, "ray-samples", case.ray_samples, flush=True)
+    img = render(Z, P, geom).cpu().numpy()
+    w = np.random.default_rng(4).standard_normal(geom.total).astype(np.float32) * 1e-3
+    gZb, gpb = render_backward(Z, P, geom, torch.from_numpy(w).to(DEV))
+    gZb = gZb.cpu().numpy()
+    gpb = gpb.cpu().numpy()
+    gZp = torch.zeros_like(Z)
+    for p in range(len(case.fans)):
+        g1 = Geometry(case.Z.shape, case.spacing, case.origin, [case.fans[p]], case.phys)
+        one = render(Z, P[p:p + 1].contiguous(), g1).cpu().numpy()
+        o = geom.offsets
+        np.testing.assert_array_equal(one, img[o[p]:o[p + 1]])
+        _, gp1 = render_backward(Z, P[p:p + 1].contiguous(), g1, torch.from_numpy(w[o[p]:o[p + 1]]).to(DEV),
+                                 grad_Z=gZp)
+        np.testing.assert_allclose(gp1.cpu().numpy()[0], gpb[p], rtol=1e-5,
+                                   atol=1e-6 * np.abs(gpb[p]).max())
+    assert H.rel_l2(gZp.cpu().numpy(), gZb) <= 1e-6
+    S = [f.n_samples for f in case.fans]
+    R = [f.n_rays * (f.aperture) for f in case.fans]
+    picks = sorted({int(np.argmax(S)), int(np.argmax(R)), 7, 33})
+    for p in picks:
+        sub = synth.Case(case.name, case.Z, case.spacing, case.origin, case.poses[p:p + 1],
+                         [case.fans[p]], case.phys)
+        ref = H.oracle_render(sub)
+        o = geom.offsets
+        rep = H.parity_report(img[o[p]:o[p + 1]], ref)
+        print("pose", p, case.fans[p], rep, flush=True)
+        assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
+
+
+def test_schedules_agree():
+    from paper_2508_06768_amd.render import get_schedule, render, render_backward, set_schedule
+    from tests.test_gpu_parity import ragged_case
+    case = ragged_case(0, 0, True, seed=31)
+    geom, Z, P = _gpu(case)
+    w = torch.from_numpy(np.random.default_rng(5).standard_normal(geom.total).astype(np.float32)).to(DEV)
+    base = get_schedule()
+    outs = []
+    try:
+        for fc, bc, xg in [(4, 4, 1), (8, 8, 16), (16, 4, 64), (8, 4, 3)]:
+            set_schedule(fwd_chunk=fc, bwd_chunk=bc, xcd_group=xg)
+            img = render(Z, P, geom).cpu().numpy().astype(np.float64)
+            gZ, gp = render_backward(Z, P, geom, w)
+            outs.append((img, gZ.cpu().numpy().astype(np.float64), gp.cpu().numpy().astype(np.float64)))
+    finally:
+        set_schedule(**base)
+    for img, gZ, gp in outs[1:]:
+        assert H.rel_l2(img, outs[0][0]) <= 1e-7
+        assert H.rel_l2(gZ, outs[0][1]) <= 1e-6
+        assert H.rel_l2(gp, outs[0][2]) <= 1e-6
+
+
+def test_graph_replays_agree():
+    from paper_2508_06768_amd.render import FusedStep, render
+    from tests.test_gpu_parity import ragged_case
+    case = ragged_case(0, 0, True, seed=41)
+    geom, Z, P = _gpu(case)
+    T = render(Z, P + 0.3, geom).clone()
+    step = FusedStep(geom, zero_grad_z=True)
+    bm = torch.empty(geom.total, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    gZ = torch.empty_like(Z)
+    gp = torch.empty((geom.n_poses, 6), device=DEV)
+    res = []
+    for it in range(4):
+        step.step(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+        torch.cuda.synchronize()
+        res.append((bm.cpu().numpy().copy(), loss.item(), gZ.cpu().numpy().copy(), gp.cpu().numpy().copy()))
+        _ = (Z * 2).sum().item()            # unrelated eager work between replays
+    eager = FusedStep(geom, zero_grad_z=True, graph=False)
+    eager.step(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+    torch.cuda.synchronize()
+    ref = (bm.cpu().numpy(), loss.item(), gZ.cpu().numpy(), gp.cpu().numpy())
+    for r in res:
+        np.testing.assert_array_equal(r[0], ref[0])
+        assert r[1] == pytest.approx(ref[1], rel=1e-12)
+        assert H.rel_l2(r[2], ref[2]) <= 1e-6
+        assert H.rel_l2(r[3], ref[3]) <= 1e-6
+
+
+def test_edge_sizes():
+    """Maximum samples per ray, single ray, one and two samples, an empty fan,
+    and a volume with 2-voxel axes."""
+    from paper_2508_06768_amd.render import render, render_backward
+    Z = synth.brain_volume(9, 32, 1.0, semi_range=(2.0, 8.0))
+    Z2 = np.ascontiguousarray(Z[:2, :2, :])                      # nz = ny = 2
+    for Zv, fans, poses in [
+        (Z, [synth.FanSpec(1, 16384, 0.0, 0.002, 0.0, 0)], [[15.5, 15.5, 0.0, 0.01, 0.02, 0.0]]),
+        (Z, [synth.FanSpec(3, 1, 0.2, 0.5, 0.0, 0), synth.FanSpec(0, 50, 0.2, 0.5, 0.0, 1),
+             synth.FanSpec(5, 2, 0.9, 0.7, 2.0, 2), synth.FanSpec(2, 300, 0.3, 0.1, 0.0, 3)],
+         [[15.5, 15.5, 0.0, 0, 0, 0]] * 4),
+        (Z2, [synth.FanSpec(4, 120, 1.0, 0.25, 0.0, 0)], [[15.0, 0.5, 0.5, 0.0, 1.5707, 0.0]]),
+    ]:
+        case = synth.Case("edge", Zv, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), np.asarray(poses, np.float32), fans,
+                          synth.PhysicsSpec(speckle_on=True, blur_on=True, seed=3))
+        geom, Zt, P = _gpu(case)
+        print("edge case", [(f.n_rays, f.n_samples) for f in fans], Zv.shape, flush=True)
+        img = render(Zt, P, geom).cpu().numpy()
+        ref = H.oracle_render(case)
+        if np.abs(ref).max() > 0:
+            rep = H.parity_report(img, ref)
+            print(rep, flush=True)
+            assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
+        else:
+            assert np.all(img == 0)
+        w = np.random.default_rng(2).standard_normal(geom.total).astype(np.float32)
+        gZ, gp = render_backward(Zt, P, geom, torch.from_numpy(w).to(DEV))
+        rV, rp = H.oracle_backward(case, w.astype(np.float64))
+        if np.abs(rV).max() > 0:
+            assert H.rel_l2(gZ.cpu().numpy(), rV) <= 1e-5
+        for p in range(len(fans)):
+            assert np.all(np.abs(gp.cpu().numpy()[p] - rp[p]) <= 1e-5 * np.linalg.norm(rp[p]) + 1e-30)
