@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default="", help="reuse / store the tuned schedule in this JSON file")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this renderer build has no multi-GPU path "
@@ -121,6 +123,13 @@ def main():
     def fused():
         step.step(Z, poses, target, loss=loss, grad_Z=gZ, grad_pose=gp)
 
+    tune = None
+    if not args.no_tune:
+        from paper_2508_06768_amd.autotune import autotune
+        if args.tune_cache:
+            os.environ["DUS_AUTOTUNE_CACHE"] = args.tune_cache
+        tune = autotune(step, fused, reps=3, use_cache=bool(args.tune_cache))
+        log(f"bench: autotuned schedule {tune['schedule']} ({tune['ms']:.3f} ms)")
     for _ in range(args.warmup):
         fused()
     torch.cuda.synchronize()
@@ -162,6 +171,8 @@ def main():
     ph1 = copy.copy(case.phys)
     ph1.blur_on = False
     g_nb = Geometry(case.Z.shape, case.spacing, case.origin, case.fans, ph1)
+    from paper_2508_06768_amd.render import set_schedule
+    set_schedule(**step.get_schedule())
     ws_b = g_nb.workspace(True, dev)
     ms_k_fwd = timed(lambda: render(Z, poses, g_nb, out=out), 10, ev)
     gsrc = torch.randn(N, device=dev) * 1e-6
@@ -214,6 +225,8 @@ def main():
             "frac": kern[dom]["GBs"] / HBM_PEAK_GBS,
             "traffic": None,
         },
+        "schedule": step.get_schedule(),
+        "autotune_trials": None if tune is None else tune.get("trials"),
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
     }

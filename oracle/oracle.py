@@ -377,29 +377,43 @@ def loss(vol: Volume, pose, fan: Fan, phys: Physics, target: np.ndarray) -> floa
     return float(np.mean(d * d))
 
 
+def _central(f, h: float, richardson: bool) -> float:
+    """Central difference of f at 0 with step h; with richardson, the
+    extrapolation (4 D(h/2) - D(h)) / 3, exact to O(h^4)."""
+    d1 = (f(h) - f(-h)) / (2 * h)
+    if not richardson:
+        return d1
+    d2 = (f(h / 2) - f(-h / 2)) / h
+    return (4 * d2 - d1) / 3
+
+
 def fd_pose(vol: Volume, pose, fan: Fan, phys: Physics, target: np.ndarray,
-            h_t: float = 1e-4, h_w: float = 1e-6) -> np.ndarray:
+            h_t: float = 1e-4, h_w: float = 1e-6, richardson: bool = False) -> np.ndarray:
     p = _pose(pose)
+    target = np.asarray(target, dtype=np.float64).reshape(fan.n_rays, fan.n_samples)
     g = np.zeros(6)
     for i in range(6):
-        h = h_t if i < 3 else h_w
-        pp, pm = p.copy(), p.copy()
-        pp[i] += h
-        pm[i] -= h
-        g[i] = (loss(vol, pp, fan, phys, target) - loss(vol, pm, fan, phys, target)) / (2 * h)
+        def f(d, i=i):
+            q = p.copy()
+            q[i] += d
+            return loss(vol, q, fan, phys, target)
+        g[i] = _central(f, h_t if i < 3 else h_w, richardson)
     return g
 
 
 def fd_voxels(vol: Volume, pose, fan: Fan, phys: Physics, target: np.ndarray, flat_idx,
-              h: float = 1e-6) -> np.ndarray:
+              h: float = 1e-6, richardson: bool = False) -> np.ndarray:
     out = np.zeros(len(flat_idx))
     flat = vol.Z.reshape(-1)
+    target = np.asarray(target, dtype=np.float64).reshape(fan.n_rays, fan.n_samples)
     for n, i in enumerate(flat_idx):
         z0 = flat[i]
-        flat[i] = z0 + h
-        lp = loss(vol, pose, fan, phys, target)
-        flat[i] = z0 - h
-        lm = loss(vol, pose, fan, phys, target)
-        flat[i] = z0
-        out[n] = (lp - lm) / (2 * h)
+
+        def f(d):
+            flat[i] = z0 + d
+            try:
+                return loss(vol, pose, fan, phys, target)
+            finally:
+                flat[i] = z0
+        out[n] = _central(f, h, richardson)
     return out

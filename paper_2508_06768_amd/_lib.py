@@ -41,7 +41,7 @@ class DusPhysics(ctypes.Structure):
 
 
 class DusSchedule(ctypes.Structure):
-    _fields_ = [("fwd_chunk", c_i32), ("bwd_chunk", c_i32), ("xcd_group", c_i32), ("reserved", c_i32)]
+    _fields_ = [("fwd_chunk", c_i32), ("bwd_chunk", c_i32), ("xcd_group", c_i32), ("scatter_rays", c_i32)]
 
 
 # every symbol include/diffus.h declares, with (restype, argtypes)

@@ -40,6 +40,7 @@ bool finite_f(float x) { return isfinite(x) != 0; }
 constexpr int kDefaultFwdChunk = 8;
 constexpr int kDefaultBwdChunk = 4;
 constexpr int kDefaultXcdGroup = 16;
+constexpr int kDefaultScatterRays = 4;
 
 int check_volume(const dus_volume *v)
 {
@@ -185,7 +186,7 @@ std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses)
             r.pose = grp[q];
             r.pivot_begin = pivot_begin[grp[q]];
             rays += f.n_rays;
-            blks += ((f.n_samples + 63) / 64) * ((f.n_rays + 15) / 16);
+            blks += ((f.n_samples + 63) / 64) * ((f.n_rays + 63) / 64);
         }
         t.total_rays = rays;
         t.total_blur_blocks = blks;
@@ -266,6 +267,7 @@ struct Sched {
     int fwd_chunk = kDefaultFwdChunk;
     int bwd_chunk = kDefaultBwdChunk;
     int xcd_group = kDefaultXcdGroup;
+    int scatter_rays = kDefaultScatterRays;
 };
 
 Sched g_sched;     // schedule of the direct (non-plan) calls
@@ -275,6 +277,9 @@ int make_sched(const dus_schedule *sc, Sched &n)
     n.fwd_chunk = sc->fwd_chunk ? sc->fwd_chunk : kDefaultFwdChunk;
     n.bwd_chunk = sc->bwd_chunk ? sc->bwd_chunk : kDefaultBwdChunk;
     n.xcd_group = sc->xcd_group ? sc->xcd_group : kDefaultXcdGroup;
+    n.scatter_rays = sc->scatter_rays ? sc->scatter_rays : kDefaultScatterRays;
+    if (n.scatter_rays != 2 && n.scatter_rays != 4 && n.scatter_rays != 8)
+        return fail(DUS_EINVAL, "scatter_rays must be 2, 4 or 8");
     if (n.fwd_chunk != 4 && n.fwd_chunk != 8 && n.fwd_chunk != 16) return fail(DUS_EINVAL, "fwd_chunk must be 4, 8 or 16");
     if (n.bwd_chunk != 4 && n.bwd_chunk != 8) return fail(DUS_EINVAL, "bwd_chunk must be 4 or 8");
     if (n.xcd_group < 1 || n.xcd_group > 64) return fail(DUS_EINVAL, "xcd_group must be in [1, 64]");
@@ -389,7 +394,7 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
             src = eb;
         }
         for (const auto &t : tabs)
-            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, src, nullptr,
+            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, src, nullptr,
                                          reinterpret_cast<float *>((char *)ws + L.zb), grad_Z,
                                          grad_pose ? acc : nullptr, nullptr, st),
                     "adjoint kernel launch");
@@ -518,7 +523,7 @@ int dus_get_schedule(dus_schedule *sc)
     sc->fwd_chunk = g_sched.fwd_chunk;
     sc->bwd_chunk = g_sched.bwd_chunk;
     sc->xcd_group = g_sched.xcd_group;
-    sc->reserved = 0;
+    sc->scatter_rays = g_sched.scatter_rays;
     return DUS_OK;
 }
 
@@ -528,7 +533,7 @@ int dus_plan_get_schedule(const dus_plan *p, dus_schedule *sc)
     sc->fwd_chunk = p->sched.fwd_chunk;
     sc->bwd_chunk = p->sched.bwd_chunk;
     sc->xcd_group = p->sched.xcd_group;
-    sc->reserved = 0;
+    sc->scatter_rays = p->sched.scatter_rays;
     return DUS_OK;
 }
 
@@ -553,11 +558,10 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         int s;
         if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, pre, nullptr, st)) != DUS_OK) return s;
         for (const auto &t : p->tabs)
-            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, loss, st), "blur/loss kernel");
-        for (const auto &t : p->tabs) DUS_HIP(dus::launch_blur(true, pa, t, res, eb, st), "blur^T kernel");
+            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, eb, loss, st), "blur/loss kernel");
         if (gZ || grad_pose)
             for (const auto &t : p->tabs)
-                DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, nullptr, zbar, gZ,
+                DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, eb, nullptr, zbar, gZ,
                                              grad_pose ? acc : nullptr, nullptr, st),
                         "adjoint kernel");
     } else {
@@ -566,7 +570,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
             if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st)) != DUS_OK) return s;
         }
         for (const auto &t : p->tabs)
-            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, nullptr, target, zbar, gZ,
+            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, nullptr, target, zbar, gZ,
                                          grad_pose ? acc : nullptr, loss, st),
                     "fused adjoint kernel");
     }

@@ -56,15 +56,17 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
                           const FanTable &t, const float *poses, float *out,
                           float *min_pivot, int pivot_base, hipStream_t st);
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter
-hipError_t launch_backward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
-                           const FanTable &t, const float *poses, const float *gsrc,
-                           const float *target, float *zbar, float *gZ, double *pose_acc,
-                           double *loss, hipStream_t st);
+hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
+                           const PhysArgs &p, const FanTable &t, const float *poses,
+                           const float *gsrc, const float *target, float *zbar, float *gZ,
+                           double *pose_acc, double *loss, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st);
+// image = B pre (optional), ebar = B^T (2 (image - target) / P), loss += MSE;
+// resid is scratch for the two-pass form used with very wide blurs
 hipError_t launch_blur_residual(const PhysArgs &p, const FanTable &t, const float *pre,
-                                const float *target, float *image, float *resid, double *loss,
-                                hipStream_t st);
+                                const float *target, float *image, float *resid, float *ebar,
+                                double *loss, hipStream_t st);
 hipError_t launch_pose_finalize(const double *acc, const float *poses, int n_poses,
                                 float *grad_pose, hipStream_t st);
 hipError_t launch_footprint(const VolArgs &v, const FanTable &t, const float *poses, uint8_t *mask,

@@ -193,18 +193,18 @@ __device__ __forceinline__ void axis_cell(double u, int n, int &i0, double &f)
 
 struct Stencil {
     int idx;               // flat index of the (x0, y0, z0) corner
+    int ix, iy, iz;        // that corner's voxel coordinates
     double fx, fy, fz;
 };
 
 __device__ __forceinline__ Stencil stencil_at(const VolArgs &v, const Ray &ray, int k)
 {
     Stencil s;
-    int ix, iy, iz;
     const double kk = (double)k;
-    axis_cell(fma(kk, ray.du[0], ray.u0[0]), v.nx, ix, s.fx);
-    axis_cell(fma(kk, ray.du[1], ray.u0[1]), v.ny, iy, s.fy);
-    axis_cell(fma(kk, ray.du[2], ray.u0[2]), v.nz, iz, s.fz);
-    s.idx = (iz * v.ny + iy) * v.nx + ix;
+    axis_cell(fma(kk, ray.du[0], ray.u0[0]), v.nx, s.ix, s.fx);
+    axis_cell(fma(kk, ray.du[1], ray.u0[1]), v.ny, s.iy, s.fy);
+    axis_cell(fma(kk, ray.du[2], ray.u0[2]), v.nz, s.iz, s.fz);
+    s.idx = (s.iz * v.ny + s.iy) * v.nx + s.ix;
     return s;
 }
 
@@ -851,8 +851,10 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
                                                      const float *__restrict__ zbar, float *__restrict__ gZ,
                                                      double *__restrict__ pose_acc, int xgrp)
 {
+    // s_box is all zeros between groups: cleared once here, and every flush
+    // clears the entries it reads
     __shared__ float s_box[kBoxCap];
-    __shared__ int s_bb[RB][6];
+    __shared__ int s_bb[2][RB][6];
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63;
     // block -> (fan, first ray); each fan owns ceil(n_rays / RB) blocks
@@ -875,18 +877,16 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
     const int sxy = v.nx * v.ny;
     const double ih[3] = {1.0 / (double)v.h[0], 1.0 / (double)v.h[1], 1.0 / (double)v.h[2]};
     double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
+    if (gZ)
+        for (int t = tid; t < kBoxCap; t += 64 * RB) s_box[t] = 0.0f;
+    int par = 0;
     for (int k0 = 0; k0 < S; k0 += 64) {
         const int k = k0 + lane;
         const float zbf = (ray_ok && k < S) ? zbar[obase + k] : 0.0f;
         const bool act = (zbf != 0.0f);
-        Stencil st{0, 0.0, 0.0, 0.0};
-        int ix = 0, iy = 0, iz = 0;
+        Stencil st{0, 0, 0, 0, 0.0, 0.0, 0.0};
         if (act) {
             st = stencil_at(v, ray, k);
-            iz = st.idx / sxy;
-            const int rem = st.idx - iz * sxy;
-            iy = rem / v.nx;
-            ix = rem - iy * v.nx;
             if (pose_acc) {
                 double gu[3];
                 trilinear(v.Z, v.nx, sxy, st, gu);
@@ -906,32 +906,34 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
             }
         }
         if (!gZ) continue;     // uniform over the block
-        // bounding box of the group's stencil cells
+        // bounding box of the group's stencil cells (double-buffered exchange)
         {
             const int big = 0x3fffffff;
-            const int mnx = wave_min_i(act ? ix : big), mny = wave_min_i(act ? iy : big);
-            const int mnz = wave_min_i(act ? iz : big);
-            const int mxx = wave_max_i(act ? ix : -1), mxy = wave_max_i(act ? iy : -1);
-            const int mxz = wave_max_i(act ? iz : -1);
+            const int mnx = wave_min_i(act ? st.ix : big), mny = wave_min_i(act ? st.iy : big);
+            const int mnz = wave_min_i(act ? st.iz : big);
+            const int mxx = wave_max_i(act ? st.ix : -1), mxy = wave_max_i(act ? st.iy : -1);
+            const int mxz = wave_max_i(act ? st.iz : -1);
             if (lane == 0) {
-                s_bb[w][0] = mnx; s_bb[w][1] = mny; s_bb[w][2] = mnz;
-                s_bb[w][3] = mxx; s_bb[w][4] = mxy; s_bb[w][5] = mxz;
+                s_bb[par][w][0] = mnx; s_bb[par][w][1] = mny; s_bb[par][w][2] = mnz;
+                s_bb[par][w][3] = mxx; s_bb[par][w][4] = mxy; s_bb[par][w][5] = mxz;
             }
         }
         __syncthreads();
-        int ox = s_bb[0][0], oy = s_bb[0][1], oz = s_bb[0][2];
-        int ex = s_bb[0][3], ey = s_bb[0][4], ez = s_bb[0][5];
+        int ox = s_bb[par][0][0], oy = s_bb[par][0][1], oz = s_bb[par][0][2];
+        int ex = s_bb[par][0][3], ey = s_bb[par][0][4], ez = s_bb[par][0][5];
 #pragma unroll
         for (int q = 1; q < RB; ++q) {
-            ox = min(ox, s_bb[q][0]); oy = min(oy, s_bb[q][1]); oz = min(oz, s_bb[q][2]);
-            ex = max(ex, s_bb[q][3]); ey = max(ey, s_bb[q][4]); ez = max(ez, s_bb[q][5]);
+            ox = min(ox, s_bb[par][q][0]); oy = min(oy, s_bb[par][q][1]); oz = min(oz, s_bb[par][q][2]);
+            ex = max(ex, s_bb[par][q][3]); ey = max(ey, s_bb[par][q][4]); ez = max(ez, s_bb[par][q][5]);
         }
-        __syncthreads();
+        par ^= 1;
         if (ex < 0) continue;  // nothing to scatter in this group (uniform)
         const int bx = ex - ox + 2, by = ey - oy + 2, bz = ez - oz + 2;
-        int rw = 1;
-        while (rw < bx) rw <<= 1;
-        const bool fits = (long long)rw * by * bz <= kBoxCap;
+        // odd row and plane strides: neighbouring cells along any axis land
+        // in different LDS banks
+        const int rs = bx | 1;
+        const int ps = (rs * by) | 1;
+        const bool fits = bx <= 64 && (long long)ps * bz <= kBoxCap;
         const float fx = (float)st.fx, fy = (float)st.fy, fz = (float)st.fz;
         const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
         const float wc[8] = {zbf * gx * gy * gz, zbf * fx * gy * gz, zbf * gx * fy * gz, zbf * fx * fy * gz,
@@ -946,27 +948,50 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
             }
             continue;
         }
-        const int plane = rw * by;
-        const int nbox = plane * bz;
-        for (int t = tid; t < nbox; t += 64 * RB) s_box[t] = 0.0f;
-        __syncthreads();
-        if (act) {
-            const int l = ((iz - oz) * by + (iy - oy)) * rw + (ix - ox);
-            const int off[8] = {0, 1, rw, rw + 1, plane, plane + 1, plane + rw, plane + rw + 1};
+        // consecutive samples in one cell form a run (a straight ray meets
+        // each cell once); sum each run into its first lane so that every
+        // LDS atomic instruction touches distinct addresses
+        {
+            const int key = act ? st.idx : -1 - lane;
+            float red[8];
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (wc[c] != 0.0f) atomicAdd(&s_box[l + off[c]], wc[c]);
+            for (int c = 0; c < 8; ++c) red[c] = wc[c];
+            for (int d = 1; d < 64; d <<= 1) {
+                const int kd = __shfl_down(key, d);
+                const bool same = (lane + d < 64) && (kd == key);
+                if (__ballot(same) == 0ull) break;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const float o = __shfl_down(red[c], d);
+                    if (same) red[c] += o;
+                }
+            }
+            const int kp = __shfl_up(key, 1);
+            const bool head = act && (lane == 0 || kp != key);
+            if (head) {
+                const int l = (st.iz - oz) * ps + (st.iy - oy) * rs + (st.ix - ox);
+                const int off[8] = {0, 1, rs, rs + 1, ps, ps + 1, ps + rs, ps + rs + 1};
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (red[c] != 0.0f) atomicAdd(&s_box[l + off[c]], red[c]);
+            }
         }
         __syncthreads();
+        // flush: each wave takes z-planes w, w + RB, ...; lanes cover the
+        // (row, x) pairs of a plane, consecutive lanes on consecutive x
         int lg2 = 0;
-        while ((1 << lg2) < rw) ++lg2;
-        for (int t = tid; t < nbox; t += 64 * RB) {
-            const float val = s_box[t];
-            if (val != 0.0f) {
-                const int lx = t & (rw - 1);
-                const int row = t >> lg2;
-                const int lz = row / by, ly = row - lz * by;
-                atomicAdd(gZ + ((oz + lz) * v.ny + (oy + ly)) * v.nx + (ox + lx), val);
+        while ((1 << lg2) < bx) ++lg2;
+        const int rows_per = 64 >> lg2;
+        const int lx = lane & ((1 << lg2) - 1), sub = lane >> lg2;
+        for (int lz = w; lz < bz; lz += RB) {
+            for (int ly = sub; ly < by; ly += rows_per) {
+                if (lx >= bx) continue;
+                const int t = lz * ps + ly * rs + lx;
+                const float val = s_box[t];
+                if (val != 0.0f) {
+                    s_box[t] = 0.0f;
+                    atomicAdd(gZ + ((oz + lz) * v.ny + (oy + ly)) * v.nx + (ox + lx), val);
+                }
             }
         }
         __syncthreads();
@@ -994,15 +1019,18 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
 // --------------------------------------------------------------------------
 // lateral blur (Sec. 2.4): per depth row k, a normalised Gaussian along the
 // ray index, sigma_k = s0 + (s1 - s0) k / (S - 1) rays, radius ceil(3 sigma)
-// decided in float32, edge replicate.  One block = 64 depths x 16 rays.
+// decided in float32, edge replicate.  A block of 4 wavefronts takes 64 rays
+// x 64 depths; lanes run along depth (coalesced rows), the rows it needs
+// (with the blur halo) are staged once in LDS.
+//   MODE 0: out = B in            MODE 1: out = B^T in
+//   MODE 2: image = B in, out = 2 (image - target) / P, loss += |.|^2 / P
+//   MODE 3: MODE 2 followed by B^T on the residual, in one pass (halo 2R)
 // --------------------------------------------------------------------------
-constexpr int kBlurRays = 16;
-constexpr int kBlurRmax = 32;
+constexpr int kBlurRays = 64;
 
-// weights w_|t| (t = 0..r) and tails sum_{t>=m} w_t, normalised; radius
-// returned (-1: identity row)
-__device__ __forceinline__ int blur_row(const PhysArgs &p, int S, int k, float *w, float *tail,
-                                        int stride)
+// normalised weights w_|t| (t = 0..r) and tails sum_{t >= m} w_|t| of depth
+// row k; returns the radius (-1: identity row)
+__device__ __forceinline__ int blur_row(const PhysArgs &p, int S, int k, float *w, float *tail, int stride)
 {
     const float frac = S > 1 ? __fdiv_rn((float)k, (float)(S - 1)) : 0.0f;
     const float d = __fsub_rn(p.s1, p.s0);
@@ -1010,33 +1038,61 @@ __device__ __forceinline__ int blur_row(const PhysArgs &p, int S, int k, float *
     if (!(sig >= 1e-3f)) return -1;
     int r = (int)ceilf(__fmul_rn(3.0f, sig));
     r = min(r, p.blur_rmax);
-    const double sd = (double)sig;
-    double tot = 0.0;
-    double wd[kBlurRmax + 1];
-    for (int t = 0; t <= r; ++t) {
-        wd[t] = exp(-(double)(t * t) / (2.0 * sd * sd));
-        tot += (t == 0) ? wd[t] : 2.0 * wd[t];
-    }
-    const double inv = 1.0 / tot;
-    double acc = 0.0;
+    const float c = -0.5f / (sig * sig);
+    float tot = 1.0f;
+    for (int t = 1; t <= r; ++t) tot += 2.0f * expf(c * (float)(t * t));
+    const float inv = 1.0f / tot;
+    float acc = 0.0f;
     for (int t = r; t >= 0; --t) {
-        acc += wd[t] * inv;
-        w[t * stride] = (float)(wd[t] * inv);
-        tail[t * stride] = (float)acc;
+        const float wt = expf(c * (float)(t * t)) * inv;
+        w[t * stride] = wt;
+        acc += wt;
+        tail[t * stride] = acc;
     }
     tail[(r + 1) * stride] = 0.0f;
     return r;
 }
 
-template <int MODE>   // 0: blur, 1: transpose, 2: blur + MSE residual
-__global__ __launch_bounds__(64) void k_blur(PhysArgs p, FanTable tab, const float *__restrict__ in,
-                                             const float *__restrict__ target,
-                                             float *__restrict__ out, float *__restrict__ resid,
-                                             double *__restrict__ loss_acc)
+// blur of row j (0 <= j < n) from a tile whose row 0 is global row `base`
+// (rows outside [0, n) stored clamped)
+__device__ __forceinline__ float blur_at(const float *tile, int base, int j, int r, const float *s_w, int lane)
 {
-    __shared__ float s_w[(kBlurRmax + 2) * 64];
-    __shared__ float s_tail[(kBlurRmax + 2) * 64];
-    const int lane = threadIdx.x;
+    float acc = 0.0f;
+    for (int t = -r; t <= r; ++t) acc = fmaf(s_w[(t < 0 ? -t : t) * 64 + lane], tile[(j + t - base) * 64 + lane], acc);
+    return acc;
+}
+
+// transpose of the blur at row i from a tile holding rows [base, ...) for
+// the rows q in [max(0, i - r), min(n - 1, i + r)]
+__device__ __forceinline__ float blur_t_at(const float *tile, int base, int i, int r, int n, const float *s_w,
+                                           const float *s_tail, int lane)
+{
+    const int lo = max(0, i - r), hi = min(n - 1, i + r);
+    float acc = 0.0f;
+    for (int q = lo; q <= hi; ++q) {
+        const int t = i - q;
+        float w = s_w[(t < 0 ? -t : t) * 64 + lane];
+        if (i == 0) w += s_tail[(q + 1) * 64 + lane];
+        if (i == n - 1) w += s_tail[(n - q) * 64 + lane];
+        acc = fmaf(w, tile[(q - base) * 64 + lane], acc);
+    }
+    return acc;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const float *__restrict__ in,
+                                              const float *__restrict__ target, float *__restrict__ out,
+                                              float *__restrict__ image, double *__restrict__ loss_acc)
+{
+    extern __shared__ float smem[];
+    const int R = p.blur_rmax;
+    float *s_w = smem;                                   // (R + 1) x 64
+    float *s_tail = s_w + (R + 1) * 64;                  // (R + 2) x 64
+    int *s_r = reinterpret_cast<int *>(s_tail + (R + 2) * 64);   // 64
+    float *tileA = reinterpret_cast<float *>(s_r + 64);  // input rows
+    const int halo = (MODE == 3) ? 2 * R : R;
+    float *tileB = tileA + (kBlurRays + 2 * halo) * 64;  // residual rows (MODE 3)
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int b = blockIdx.x;
     const int fi = find_blur_fan(tab, b);
     const FanRec fr = tab.f[fi];
@@ -1046,44 +1102,82 @@ __global__ __launch_bounds__(64) void k_blur(PhysArgs p, FanTable tab, const flo
     const int kb = lb % nkb, jb = lb / nkb;
     const int k = kb * 64 + lane;
     const bool active = k < S;
-    const int r = active ? blur_row(p, S, k, s_w + lane, s_tail + lane, 64) : -1;
-    const float *src = in + fr.out_offset + k;
-    const int j0 = jb * kBlurRays, j1 = active ? min(n, j0 + kBlurRays) : j0;
+    if (w == 0) s_r[lane] = active ? blur_row(p, S, k, s_w + lane, s_tail + lane, 64) : -1;
+    const int j0 = jb * kBlurRays, j1 = min(n, j0 + kBlurRays);
+    const long long col = fr.out_offset + k;
+    // stage input rows [j0 - halo, j1 + halo), clamped for the forward blur
+    const int baseA = j0 - halo, rowsA = (j1 - j0) + 2 * halo;
+    for (int q = w; q < rowsA; q += 4) {
+        const int g = baseA + q;
+        float val = 0.0f;
+        if (active) {
+            if (MODE == 1) {
+                if (g >= 0 && g < n) val = in[col + (long long)g * S];
+            } else {
+                val = in[col + (long long)min(max(g, 0), n - 1) * S];
+            }
+        }
+        tileA[q * 64 + lane] = val;
+    }
+    __syncthreads();
+    const int r = s_r[lane];
     const double inv_npix = 1.0 / ((double)n * (double)S);
     double lsum = 0.0;
-    for (int jj = j0; jj < j1; ++jj) {
-        float acc = 0.0f;
-        if (r < 0) {
-            acc = src[(long long)jj * S];
-        } else if (MODE != 1) {
-            for (int t = -r; t <= r; ++t) {
-                const int q = min(max(jj + t, 0), n - 1);
-                acc = fmaf(s_w[(t < 0 ? -t : t) * 64 + lane], src[(long long)q * S], acc);
-            }
-        } else {
-            const int lo = max(0, jj - r), hi = min(n - 1, jj + r);
-            for (int q = lo; q <= hi; ++q) {
-                const int t = jj - q;
-                float w = s_w[(t < 0 ? -t : t) * 64 + lane];
-                if (jj == 0) w += s_tail[(q + 1) * 64 + lane];
-                if (jj == n - 1) w += s_tail[(n - q) * 64 + lane];
-                acc = fmaf(w, src[(long long)q * S], acc);
+    if (MODE == 0 || MODE == 1 || MODE == 2) {
+        for (int j = j0 + w; j < j1; j += 4) {
+            if (!active) continue;
+            float acc;
+            if (r < 0) acc = tileA[(j - baseA) * 64 + lane];
+            else if (MODE == 1) acc = blur_t_at(tileA, baseA, j, r, n, s_w, s_tail, lane);
+            else acc = blur_at(tileA, baseA, j, r, s_w, lane);
+            const long long o = col + (long long)j * S;
+            if (MODE == 2) {
+                const double dd = (double)acc - (double)target[o];
+                if (image) image[o] = acc;
+                out[o] = (float)(2.0 * dd * inv_npix);
+                lsum += dd * dd * inv_npix;
+            } else {
+                out[o] = acc;
             }
         }
-        const long long o = fr.out_offset + (long long)jj * S + k;
-        if (MODE == 2) {
-            const float d = acc - target[o];
-            if (out) out[o] = acc;
-            resid[o] = (float)(2.0 * (double)d * inv_npix);
-            lsum += (double)d * (double)d * inv_npix;
-        } else {
-            out[o] = acc;
+    } else {
+        // residual rows [j0 - R, j1 + R) clipped to [0, n)
+        const int baseB = j0 - R, rowsB = (j1 - j0) + 2 * R;
+        for (int q = w; q < rowsB; q += 4) {
+            const int j = baseB + q;
+            float res = 0.0f;
+            if (active && j >= 0 && j < n) {
+                const float I = (r < 0) ? tileA[(j - baseA) * 64 + lane] : blur_at(tileA, baseA, j, r, s_w, lane);
+                const long long o = col + (long long)j * S;
+                const double dd = (double)I - (double)target[o];
+                res = (float)(2.0 * dd * inv_npix);
+                if (j >= j0 && j < j1) {
+                    lsum += dd * dd * inv_npix;
+                    if (image) image[o] = I;
+                }
+            }
+            tileB[q * 64 + lane] = res;
+        }
+        __syncthreads();
+        for (int i = j0 + w; i < j1; i += 4) {
+            if (!active) continue;
+            const float e = (r < 0) ? tileB[(i - baseB) * 64 + lane]
+                                    : blur_t_at(tileB, baseB, i, r, n, s_w, s_tail, lane);
+            out[col + (long long)i * S] = e;
         }
     }
-    if (MODE == 2 && loss_acc) {
+    if ((MODE == 2 || MODE == 3) && loss_acc) {
         lsum = wave_sum(lsum);
         if (lane == 0) atomicAdd(loss_acc, lsum);
     }
+}
+
+inline size_t blur_smem(int mode, int R)
+{
+    const int halo = (mode == 3) ? 2 * R : R;
+    size_t f = (size_t)(R + 1) * 64 + (size_t)(R + 2) * 64 + 64 + (size_t)(kBlurRays + 2 * halo) * 64;
+    if (mode == 3) f += (size_t)(kBlurRays + 2 * R) * 64;
+    return f * 4;
 }
 
 // --------------------------------------------------------------------------
@@ -1289,10 +1383,10 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
         }                                                                                      \
         break;
 
-hipError_t launch_backward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
-                           const FanTable &t, const float *poses, const float *gsrc,
-                           const float *target, float *zbar, float *gZ, double *pose_acc,
-                           double *loss, hipStream_t st)
+hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
+                           const PhysArgs &p, const FanTable &t, const float *poses,
+                           const float *gsrc, const float *target, float *zbar, float *gZ,
+                           double *pose_acc, double *loss, hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
@@ -1305,11 +1399,21 @@ hipError_t launch_backward(int chunk, int xcd_group, const VolArgs &v, const Phy
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || (!gZ && !pose_acc)) return e;
-    constexpr int RB = 4;
     int blocks = 0;
-    for (int f = 0; f < t.n; ++f) blocks += (t.f[f].n_rays + RB - 1) / RB;
-    hipLaunchKernelGGL((k_scatter<RB>), dim3(blocks), dim3(64 * RB), 0, st, v, t, poses, zbar, gZ, pose_acc,
-                       xcd_group);
+    for (int f = 0; f < t.n; ++f) blocks += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
+    switch (scatter_rays) {
+    case 2:
+        hipLaunchKernelGGL((k_scatter<2>), dim3(blocks), dim3(128), 0, st, v, t, poses, zbar, gZ, pose_acc, xcd_group);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_scatter<4>), dim3(blocks), dim3(256), 0, st, v, t, poses, zbar, gZ, pose_acc, xcd_group);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_scatter<8>), dim3(blocks), dim3(512), 0, st, v, t, poses, zbar, gZ, pose_acc, xcd_group);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1318,24 +1422,28 @@ hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, con
 {
     const int grid = t.total_blur_blocks;
     if (grid <= 0) return hipSuccess;
+    const int R = p.blur_rmax;
     if (transpose)
-        hipLaunchKernelGGL((k_blur<1>), dim3(grid), dim3(64), 0, st, p, t, in, nullptr, out,
+        hipLaunchKernelGGL((k_blur<1>), dim3(grid), dim3(256), blur_smem(1, R), st, p, t, in, nullptr, out,
                            nullptr, nullptr);
     else
-        hipLaunchKernelGGL((k_blur<0>), dim3(grid), dim3(64), 0, st, p, t, in, nullptr, out,
+        hipLaunchKernelGGL((k_blur<0>), dim3(grid), dim3(256), blur_smem(0, R), st, p, t, in, nullptr, out,
                            nullptr, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_blur_residual(const PhysArgs &p, const FanTable &t, const float *pre,
-                                const float *target, float *image, float *resid, double *loss,
-                                hipStream_t st)
+                                const float *target, float *image, float *resid, float *ebar,
+                                double *loss, hipStream_t st)
 {
     const int grid = t.total_blur_blocks;
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_blur<2>), dim3(grid), dim3(64), 0, st, p, t, pre, target, image, resid,
+    const int R = p.blur_rmax;
+    hipLaunchKernelGGL((k_blur<2>), dim3(grid), dim3(256), blur_smem(2, R), st, p, t, pre, target, resid, image,
                        loss);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_blur(true, p, t, resid, ebar, st);
 }
 
 hipError_t launch_pose_finalize(const double *acc, const float *poses, int n_poses,

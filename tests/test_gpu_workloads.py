@@ -67,7 +67,11 @@ def test_adjoint_full_size_vs_oracle_and_finite_differences():
     idx = list(rng.choice(hot, size=64, replace=False))
     cold = np.flatnonzero(flat == 0.0)
     idx_cold = list(rng.choice(cold, size=8, replace=False))
-    fd = O.fd_voxels(vol, pose, fan, ph, tf, idx + idx_cold, h=1e-6)
+    tf2 = tf.reshape(fan.n_rays, fan.n_samples)
+    # the |R| convention puts rays of this workload close to poles of the
+    # echo (min pivot 0.02, peak pixel 3e3): the loss is sharply curved, so
+    # the differences use small steps with Richardson extrapolation
+    fd = O.fd_voxels(vol, pose, fan, ph, tf2, idx + idx_cold, h=2e-7, richardson=True)
     g_sel = gZ.reshape(-1)[idx + idx_cold]
     err = np.abs(g_sel[:64] - fd[:64]) / np.abs(fd[:64])
     print("voxel FD rel err max", err.max(), "median", np.median(err), flush=True)
@@ -75,9 +79,9 @@ def test_adjoint_full_size_vs_oracle_and_finite_differences():
     assert np.all(fd[64:] == 0.0)
     assert np.linalg.norm(g_sel[:64] - fd[:64]) <= 1e-3 * np.linalg.norm(fd[:64])
     assert np.all(err <= 1e-2)
-    fdp = O.fd_pose(vol, pose, fan, ph, tf, h_t=1e-4, h_w=1e-6)
+    fdp = O.fd_pose(vol, pose, fan, ph, tf2, h_t=2e-7, h_w=2e-9, richardson=True)
     print("pose FD", fdp, "gpu", gp, flush=True)
-    assert np.linalg.norm(gp - fdp) <= 1e-3 * np.linalg.norm(fdp)
+    assert np.all(np.abs(gp - fdp) <= 1e-3 * np.abs(fdp))
 
 
 def test_batched_equals_plain_and_oracle():
