@@ -203,6 +203,7 @@ struct WsLayout {
     size_t res = 0, res_bytes = 0;     // MSE residual (plan with blur)
     size_t acc = 0, acc_bytes = 0;     // pose accumulators
     size_t zb = 0, zb_bytes = 0;       // dL/dZ per sample (adjoint)
+    size_t part = 0, part_bytes = 0;   // loss partials (plan step)
     size_t total = 0;
 };
 
@@ -234,6 +235,15 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         L.acc = off;
         L.acc_bytes = (size_t)std::max(n_poses, 1) * dus::kPoseAcc * sizeof(double);
         off = align_up(off + L.acc_bytes);
+    }
+    if (mode == 2) {
+        // one partial per blur block or per ray of every table
+        size_t n = 0;
+        for (const auto &t : build_tables(fans, n_poses))
+            n += (size_t)std::max(t.total_blur_blocks, t.total_rays);
+        L.part = off;
+        L.part_bytes = std::max<size_t>(n, 1) * sizeof(double);
+        off = align_up(off + L.part_bytes);
     }
     L.total = off;
     return L;
@@ -547,7 +557,8 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     float *zbar = reinterpret_cast<float *>((char *)ws + p->ws.zb);
     float *gZ = (p->flags & DUS_PLAN_POSE_ONLY) ? nullptr : grad_Z;
     if (grad_pose) DUS_HIP(dus::launch_zero_f64(acc, (int64_t)n_poses * dus::kPoseAcc, st), "zero kernel");
-    if (loss) DUS_HIP(dus::launch_zero_f64(loss, 1, st), "zero kernel");
+    double *part = reinterpret_cast<double *>((char *)ws + p->ws.part);
+    int64_t n_part = 0;
     if (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z))
         DUS_HIP(dus::launch_zero_f32(gZ, (int64_t)p->vol.nx * p->vol.ny * p->vol.nz, st), "zero kernel");
     const Sched &sc = p->sched;
@@ -557,8 +568,11 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         float *eb = reinterpret_cast<float *>((char *)ws + p->ws.eb);
         int s;
         if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, pre, nullptr, st)) != DUS_OK) return s;
-        for (const auto &t : p->tabs)
-            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, eb, loss, st), "blur/loss kernel");
+        for (const auto &t : p->tabs) {
+            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, eb, loss ? part + n_part : nullptr, st),
+                    "blur/loss kernel");
+            n_part += t.total_blur_blocks;
+        }
         if (gZ || grad_pose)
             for (const auto &t : p->tabs)
                 DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, eb, nullptr, zbar, gZ,
@@ -569,11 +583,14 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
             int s;
             if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st)) != DUS_OK) return s;
         }
-        for (const auto &t : p->tabs)
+        for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, nullptr, target, zbar, gZ,
-                                         grad_pose ? acc : nullptr, loss, st),
+                                         grad_pose ? acc : nullptr, loss ? part + n_part : nullptr, st),
                     "fused adjoint kernel");
+            n_part += t.total_rays;
+        }
     }
+    if (loss) DUS_HIP(dus::launch_sum_f64(part, n_part, loss, st), "loss sum kernel");
     if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel");
     return DUS_OK;
 }

@@ -55,15 +55,16 @@ constexpr int kPoseAcc = 12;
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out,
                           float *min_pivot, int pivot_base, hipStream_t st);
-// adjoint: dL/dZ per sample into zbar (image layout), then its scatter
+// adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
+// the fused form (target given) loss receives one partial per ray
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
                            double *pose_acc, double *loss, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st);
-// image = B pre (optional), ebar = B^T (2 (image - target) / P), loss += MSE;
-// resid is scratch for the two-pass form used with very wide blurs
+// image = B pre (optional), ebar = B^T (2 (image - target) / P); loss
+// receives one MSE partial per blur block (total_blur_blocks entries)
 hipError_t launch_blur_residual(const PhysArgs &p, const FanTable &t, const float *pre,
                                 const float *target, float *image, float *resid, float *ebar,
                                 double *loss, hipStream_t st);
@@ -74,6 +75,8 @@ hipError_t launch_footprint(const VolArgs &v, const FanTable &t, const float *po
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t st);
+// *out = sum of the n partials (the loss of the fused step)
+hipError_t launch_sum_f64(const double *part, int64_t n, double *out, hipStream_t st);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t st);
 hipError_t launch_pixel_gain(const PhysArgs &p, const FanRec &f, float *out, hipStream_t st);

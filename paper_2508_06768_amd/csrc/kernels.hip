@@ -815,8 +815,9 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         __syncthreads();
     }
     if (FUSED && loss_acc) {
+        // one partial per ray, summed by k_sum_f64 (no contended atomics)
         const double ls = wave_sum(loss);
-        if (lane == 0) atomicAdd(loss_acc, ls);
+        if (lane == 0) loss_acc[g] = ls;
     }
 }
 
@@ -1167,8 +1168,12 @@ __global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const fl
         }
     }
     if ((MODE == 2 || MODE == 3) && loss_acc) {
+        // one partial per block, summed by k_sum_f64 (no contended atomics)
+        __shared__ double s_part[4];
         lsum = wave_sum(lsum);
-        if (lane == 0) atomicAdd(loss_acc, lsum);
+        if (lane == 0) s_part[w] = lsum;
+        __syncthreads();
+        if (tid == 0) loss_acc[b] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
     }
 }
 
@@ -1290,6 +1295,18 @@ __global__ void k_zero_f32(float *p, long long n)
     } else {
         for (long long i = i0; i < n; i += stride) p[i] = 0.0f;
     }
+}
+
+// out = sum of n partials (single block, fixed order: deterministic)
+__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, long long n, double *__restrict__ out)
+{
+    __shared__ double s_w[4];
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256) acc += part[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
 }
 
 __global__ void k_copy_f64(const double *s, double *d, long long n)
@@ -1475,6 +1492,12 @@ hipError_t launch_zero_f32(float *ptr, int64_t n, hipStream_t st)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_f32, dim3(grid_for((n + 3) / 4, 256)), dim3(256), 0, st, ptr,
                        (long long)n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_f64(const double *part, int64_t n, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, (long long)n, out);
     return hipGetLastError();
 }
 
