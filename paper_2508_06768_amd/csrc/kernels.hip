@@ -51,6 +51,15 @@ __device__ __forceinline__ double lane_read(double x, int l)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// a wave-uniform double made visibly uniform to the compiler (kept in SGPRs)
+__device__ __forceinline__ double uniform(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xffffffffll));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_sum(double x)
 {
 #pragma unroll
@@ -82,6 +91,17 @@ __device__ __forceinline__ double div64(double a, double b)
     const double q = a * r;
     return fma(fma(-b, q, a), r, q);
 }
+
+// partial unroll of the sample-gather loops: enough independent gathers in
+// flight without holding every tile sample in registers
+#ifndef GATHER_UNROLL
+#define GATHER_UNROLL 2
+#endif
+// the adjoint's per-lane walks run one interface per iteration: unrolling
+// them only raises register pressure
+#ifndef WALK_UNROLL
+#define WALK_UNROLL 1
+#endif
 
 // LDS index padding: doubles (one pad word per 16) and floats (per 32)
 __device__ __forceinline__ int pad8(int i) { return i + (i >> 4); }
@@ -180,6 +200,17 @@ __device__ __forceinline__ void setup_ray(const VolArgs &v, const PhysArgs &p, c
     ray.dirz = cz;
     ray.r0 = r0;
     ray.ds = ds;
+    // every lane computed the same values: keep them in scalar registers
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ray.u0[a] = uniform(ray.u0[a]);
+        ray.du[a] = uniform(ray.du[a]);
+    }
+    ray.a2 = uniform(ray.a2);
+    ray.dirx = uniform(ray.dirx);
+    ray.dirz = uniform(ray.dirz);
+    ray.r0 = uniform(ray.r0);
+    ray.ds = uniform(ray.ds);
 }
 
 // cell index (clamped) and fraction along one axis; NaN positions clamp to 0
@@ -330,18 +361,20 @@ __device__ __forceinline__ float posthoc_coef(const PhysArgs &p, float ds)
 // phase 1: gather samples [t0, t0+T) of a ray, interface rho of (k-1, k)
 // into s_rho[pad8(k - t0)]; optionally keep the samples in s_z.
 // --------------------------------------------------------------------------
-template <int C, bool KEEPZ>
+template <int C, bool KEEPZ, bool KEEPG = false>
 __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, int t0, int S,
                                             bool absm, int lane, double &zprev, double *s_rho,
-                                            double *s_z)
+                                            double *s_z, float *s_g = nullptr)
 {
+    constexpr int T = 64 * C;
     const int sxy = v.nx * v.ny;
-#pragma unroll
+#pragma unroll GATHER_UNROLL
     for (int jj = 0; jj < C; ++jj) {
         const int i = jj * 64 + lane;
         const int k = t0 + i;
         const Stencil st = stencil_at(v, ray, min(k, S - 1));
-        const double z = trilinear(v.Z, v.nx, sxy, st, nullptr);
+        double gu[3];
+        const double z = trilinear(v.Z, v.nx, sxy, st, KEEPG ? gu : nullptr);
         double zm = __shfl_up(z, 1);
         if (lane == 0) zm = zprev;
         zprev = lane_read(z, 63);
@@ -349,6 +382,11 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
         if (k >= 1 && k < S) rho = iface_rho(zm, z, absm);
         s_rho[pad8(i)] = rho;
         if (KEEPZ) s_z[pad8(i)] = z;
+        if (KEEPG) {
+            s_g[i] = (float)gu[0];
+            s_g[T + i] = (float)gu[1];
+            s_g[2 * T + i] = (float)gu[2];
+        }
     }
 }
 
@@ -398,7 +436,7 @@ __device__ __forceinline__ void chunk_product(const double *s_rho, int base, int
 {
     Q = Mat{1.0, 0.0, 0.0, 1.0};
     qd = 1.0;
-#pragma unroll
+#pragma unroll 1
     for (int i = 0; i < C; ++i) {
         const int k = t0 + base + i;
         const bool valid = (k >= 1) && (k < S);
@@ -521,7 +559,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             cD = ldexp(nD, -2 * ex);
         }
         __syncthreads();
-#pragma unroll
+#pragma unroll 1
         for (int m = 0; m < C; ++m) {
             const int i = m * 64 + lane;
             const int k = t0 + i;
@@ -579,10 +617,12 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                                                  const float *__restrict__ gsrc,
                                                  const float *__restrict__ target,
                                                  float *__restrict__ zbar,
+                                                 double *__restrict__ pose_acc,
                                                  double *__restrict__ loss_acc, int xgrp)
 {
     constexpr int T = 64 * C;
     constexpr int kMaxTiles = (DUS_MAX_SAMPLES + T - 1) / T;
+    __shared__ float s_g[3 * T];     // dZ/du of every sample of the tile
     __shared__ double s_rho[T + T / 16];
     __shared__ double s_z[T + T / 16];
     __shared__ float s_eb[T + T / 32];
@@ -645,16 +685,21 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     double rbar_next = 0.0;        // rho-bar of the interface just after this tile
     double z_next = 0.0;           // first sample of the next tile
     double loss = 0.0;
+    double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
+    const double ih[3] = {1.0 / (double)v.h[0], 1.0 / (double)v.h[1], 1.0 / (double)v.h[2]};
     for (int t = ntiles - 1; t >= 0; --t) {
         const int t0 = t * T;
         const double c0 = s_carry[t][0], c1 = s_carry[t][1], cD = s_carry[t][2];
         const double zstart = s_carry[t][3];
         double zprev = zstart;
-        gather_tile<C, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z);
+        if (pose_acc)
+            gather_tile<C, true, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g);
+        else
+            gather_tile<C, true, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z);
         if (SPK) speckle_fill<T>(p, t0, j, fr.speckle_id, lane, s_xig, s_xir);
         __syncthreads();
         // dL/de (or the target for the fused loss) staged through LDS
-#pragma unroll
+#pragma unroll 1
         for (int m = 0; m < C; ++m) {
             const int i = m * 64 + lane;
             const int k = t0 + i;
@@ -674,30 +719,47 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         double qd, xd, td;
         chunk_product<C>(s_rho, base, t0, S, a2, sgn, Q, qd);
         scan_exclusive(lane, Q, qd, X, xd, Tot, td);
-        // forward walk: states before each step
-        double sv0[C], sv1[C], sD[C];
+        // Walk 1 (forward over the lane's C interfaces): the chunk's affine
+        // adjoint map lambda_start = lambda_end J_chunk + f_chunk, with
+        // J_chunk = diag(Q^T, det) and f_chunk = sum_i f_i (Q_i^loc)^T, where
+        // Q_i^loc = M_first .. M_{i-1} and f_i is step i's forcing (adj_forcing).
+        const double v0s = fma(c0, X.a, c1 * X.c);
+        const double v1s = fma(c0, X.b, c1 * X.d);
+        const double Ds = cD * xd;
+        Adj f{0.0, 0.0, 0.0};
         {
-            double v0 = fma(c0, X.a, c1 * X.c);
-            double v1 = fma(c0, X.b, c1 * X.d);
-            double D = cD * xd;
-#pragma unroll
+            double v0 = v0s, v1 = v1s, D = Ds;
+            Mat QL{1.0, 0.0, 0.0, 1.0};
+            double qdl = 1.0;
+#pragma unroll WALK_UNROLL
             for (int i = 0; i < C; ++i) {
                 const int k = t0 + base + i;
-                const bool valid = (k >= 1) && (k < S);
-                sv0[i] = v0;
-                sv1[i] = v1;
-                sD[i] = D;
-                if (valid) {
+                if (k >= 1 && k < S) {
                     const double r = s_rho[pad8(base + i)];
                     const Map m = make_map(r, a2, sgn, true);
                     const double v1n = fma(v0, r, v1);
+                    const double w1 = rcp64(v1), w1p = rcp64(v1n);
+                    const double e = r * D * w1 * w1p;
+                    double eb;
                     if (FUSED) {
-                        const double e = r * D * rcp64(v1 * v1n);
                         const double gn = s_gain[pad4(base + i)];
                         const double diff = e * gn - (double)s_eb[pad4(base + i)];
                         loss += diff * diff * inv_npix;
-                        s_eb[pad4(base + i)] = (float)(2.0 * diff * inv_npix * gn);
+                        eb = 2.0 * diff * inv_npix * gn;
+                        s_eb[pad4(base + i)] = (float)eb;
+                    } else {
+                        eb = s_eb[pad4(base + i)];
                     }
+                    const double f0 = -eb * e * r * w1p;
+                    const double f1 = -eb * e * (w1 + w1p);
+                    const double fD = eb * r * w1 * w1p;
+                    f.l0 = fma(f0, QL.a, fma(f1, QL.b, f.l0));
+                    f.l1 = fma(f0, QL.c, fma(f1, QL.d, f.l1));
+                    f.lD = fma(fD, qdl, f.lD);
+                    const double n00 = fma(QL.a, m.m00, QL.b * m.m10), n01 = fma(QL.a, r, QL.b);
+                    const double n10 = fma(QL.c, m.m00, QL.d * m.m10), n11 = fma(QL.c, r, QL.d);
+                    QL = Mat{n00, n01, n10, n11};
+                    qdl *= m.det;
                     const double v0n = fma(v0, m.m00, v1 * m.m10);
                     v0 = v0n;
                     v1 = v1n;
@@ -706,16 +768,6 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                     const double diff = -(double)s_eb[pad4(base + i)];
                     loss += diff * diff * inv_npix;
                 }
-            }
-        }
-        // chunk's affine map: lambda_start = lambda_end J + f (f from lambda_end = 0)
-        Adj f{0.0, 0.0, 0.0};
-#pragma unroll
-        for (int i = C - 1; i >= 0; --i) {
-            const int k = t0 + base + i;
-            if (k >= 1 && k < S) {
-                double rb;
-                f = adj_step(f, sv0[i], sv1[i], sD[i], s_rho[pad8(base + i)], a2, sgn, s_eb[pad4(base + i)], rb);
             }
         }
         // suffix composition over lanes: Psi_l = Phi_l o Phi_{l+1} o ... o Phi_63
@@ -761,20 +813,53 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                 le.lD = fma(lam.lD, nd, nfD);
             }
         }
-        // final reverse walk: rho-bar of every interface
-        __syncthreads();
-#pragma unroll
-        for (int i = C - 1; i >= 0; --i) {
-            const int k = t0 + base + i;
-            double rb = 0.0;
-            if (k >= 1 && k < S)
-                le = adj_step(le, sv0[i], sv1[i], sD[i], s_rho[pad8(base + i)], a2, sgn, s_eb[pad4(base + i)], rb);
-            s_rho[pad8(base + i)] = rb;       // s_rho now holds rho-bar
+        // adjoint at the lane's chunk start: lambda_end J_chunk + f_chunk
+        Adj lc;
+        lc.l0 = fma(le.l0, Q.a, fma(le.l1, Q.b, f.l0));
+        lc.l1 = fma(le.l0, Q.c, fma(le.l1, Q.d, f.l1));
+        lc.lD = fma(le.lD, qd, f.lD);
+        const Adj lstart = lc;
+        // Walk 2 (forward again): the adjoint after step i follows from the
+        // one before it by the exact inverse of step i,
+        //   lambda_{i+1} = (lambda_i - f_i) J_i^{-1},  det M_i = a^2 (1 - rho^2) > 0,
+        // and gives dL/drho_i (adj_rbar).
+        {
+            double v0 = v0s, v1 = v1s, D = Ds;
+#pragma unroll WALK_UNROLL
+            for (int i = 0; i < C; ++i) {
+                const int k = t0 + base + i;
+                double rb = 0.0;
+                if (k >= 1 && k < S) {
+                    const double r = s_rho[pad8(base + i)];
+                    const Map m = make_map(r, a2, sgn, true);
+                    const double v1n = fma(v0, r, v1);
+                    const double w1 = rcp64(v1), w1p = rcp64(v1n);
+                    const double e = r * D * w1 * w1p;
+                    const double eb = s_eb[pad4(base + i)];
+                    const double x0 = lc.l0 + eb * e * r * w1p;
+                    const double x1 = lc.l1 + eb * e * (w1 + w1p);
+                    const double xD = lc.lD - eb * r * w1 * w1p;
+                    const double ie = rcp64(m.det);
+                    // M = [[A, r], [B, 1]]:  x (M^T)^{-1} = (x0 - r x1, A x1 - B x0) / det
+                    const Adj la{(x0 - r * x1) * ie, fma(m.m00, x1, -m.m10 * x0) * ie, xD * ie};
+                    const double dA = -2.0 * a2 * r * (1.0 + sgn);
+                    const double dB = -a2 * sgn;
+                    const double dE = -2.0 * a2 * r;
+                    rb = la.l0 * fma(v0, dA, v1 * dB) + la.l1 * v0 + eb * D * w1p * w1p + la.lD * D * dE;
+                    lc = la;
+                    const double v0n = fma(v0, m.m00, v1 * m.m10);
+                    v0 = v0n;
+                    v1 = v1n;
+                    D *= m.det;
+                }
+                s_rho[pad8(base + i)] = rb;       // s_rho now holds rho-bar
+            }
         }
+        le = lstart;
         // adjoint of this tile's start state, expressed for the previous tile's
         // (un-renormalised) end state
         {
-            Adj ls{lane_read(le.l0, 0), lane_read(le.l1, 0), lane_read(le.lD, 0)};
+            Adj ls{lane_read(le.l0, 0), lane_read(le.l1, 0), lane_read(le.lD, 0)};   // le = chunk-start adjoint
             const int ex = (t > 0) ? s_cexp[t] : 0;
             lam.l0 = ldexp(ls.l0, -ex);
             lam.l1 = ldexp(ls.l1, -ex);
@@ -783,7 +868,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         __syncthreads();
 
         // dL/dZ_k per sample (rho depends on the samples on both sides)
-#pragma unroll
+#pragma unroll 1
         for (int jj = 0; jj < C; ++jj) {
             const int i = jj * 64 + lane;
             const int k = t0 + i;
@@ -809,10 +894,43 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                 zb = fma(rr, dz, zb);
             }
             zbar[obase + k] = (float)zb;
+            if (pose_acc && zb != 0.0) {
+                // dL/dp = zb dZ/du / h per axis (0 where the sample is clamped);
+                // dL/dR accumulates (s_k dir) outer dL/dp
+                const double kk = (double)k;
+                const double sk = fma(kk, ray.ds, ray.r0);
+                const int n[3] = {v.nx, v.ny, v.nz};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double u = fma(kk, ray.du[a], ray.u0[a]);
+                    const bool inside = (u >= 0.0) && (u <= (double)(n[a] - 1));
+                    const double gp = inside ? zb * (double)s_g[a * T + i] * ih[a] : 0.0;
+                    gsum[a] += gp;
+                    gssum[a] = fma(sk, gp, gssum[a]);
+                }
+            }
         }
         rbar_next = lane_read(s_rho[pad8(lane)], 0);
         z_next = lane_read(s_z[pad8(lane)], 0);
         __syncthreads();
+    }
+    if (pose_acc) {
+        double r[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r[a] = wave_sum(gsum[a]);
+            r[3 + a] = wave_sum(gssum[a]);
+        }
+        if (lane == 0) {
+            double *pa = pose_acc + (size_t)kPoseAcc * fr.pose;
+            // dL/dt = sum g;  dL/dR = sum g (s dir)^T, dir = (sx, 0, cz)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                atomicAdd(pa + a, r[a]);
+                atomicAdd(pa + 3 + 3 * a + 0, r[3 + a] * ray.dirx);
+                atomicAdd(pa + 3 + 3 * a + 2, r[3 + a] * ray.dirz);
+            }
+        }
     }
     if (FUSED && loss_acc) {
         // one partial per ray, summed by k_sum_f64 (no contended atomics)
@@ -850,7 +968,7 @@ __device__ __forceinline__ int wave_max_i(int x)
 template <int RB>
 __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, const float *__restrict__ poses,
                                                      const float *__restrict__ zbar, float *__restrict__ gZ,
-                                                     double *__restrict__ pose_acc, int xgrp)
+                                                     int xgrp)
 {
     // s_box is all zeros between groups: cleared once here, and every flush
     // clears the entries it reads
@@ -876,47 +994,37 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
     setup_ray(v, p, fr, poses, ray_ok ? j : 0, ray);
     const long long obase = fr.out_offset + (long long)j * S;
     const int sxy = v.nx * v.ny;
-    const double ih[3] = {1.0 / (double)v.h[0], 1.0 / (double)v.h[1], 1.0 / (double)v.h[2]};
-    double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
-    if (gZ)
-        for (int t = tid; t < kBoxCap; t += 64 * RB) s_box[t] = 0.0f;
+    for (int t = tid; t < kBoxCap; t += 64 * RB) s_box[t] = 0.0f;
     int par = 0;
+    // dL/dZ of the next group is loaded one group ahead
+    float zb_next = (ray_ok && lane < S) ? zbar[obase + lane] : 0.0f;
     for (int k0 = 0; k0 < S; k0 += 64) {
         const int k = k0 + lane;
-        const float zbf = (ray_ok && k < S) ? zbar[obase + k] : 0.0f;
+        const float zbf = zb_next;
+        zb_next = (ray_ok && k + 64 < S) ? zbar[obase + k + 64] : 0.0f;
         const bool act = (zbf != 0.0f);
         Stencil st{0, 0, 0, 0, 0.0, 0.0, 0.0};
-        if (act) {
-            st = stencil_at(v, ray, k);
-            if (pose_acc) {
-                double gu[3];
-                trilinear(v.Z, v.nx, sxy, st, gu);
-                const double kk = (double)k;
-                const double u[3] = {fma(kk, ray.du[0], ray.u0[0]), fma(kk, ray.du[1], ray.u0[1]),
-                                     fma(kk, ray.du[2], ray.u0[2])};
-                const int n[3] = {v.nx, v.ny, v.nz};
-                const double sk = fma(kk, ray.ds, ray.r0);
-                const double zb = (double)zbf;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const bool inside = (u[a] >= 0.0) && (u[a] <= (double)(n[a] - 1));
-                    const double gp = inside ? zb * gu[a] * ih[a] : 0.0;
-                    gsum[a] += gp;
-                    gssum[a] = fma(sk, gp, gssum[a]);
+        if (act) st = stencil_at(v, ray, k);
+        // bounding box of the group's stencil cells: cell coordinates are
+        // monotone along a straight ray, so the extremes sit at the first
+        // and the last active lane (double-buffered exchange between waves)
+        {
+            const unsigned long long am = __ballot(act);
+            if (lane == 0) {
+                if (am == 0ull) {
+                    s_bb[par][w][0] = s_bb[par][w][1] = s_bb[par][w][2] = 0x3fffffff;
+                    s_bb[par][w][3] = s_bb[par][w][4] = s_bb[par][w][5] = -1;
                 }
             }
-        }
-        if (!gZ) continue;     // uniform over the block
-        // bounding box of the group's stencil cells (double-buffered exchange)
-        {
-            const int big = 0x3fffffff;
-            const int mnx = wave_min_i(act ? st.ix : big), mny = wave_min_i(act ? st.iy : big);
-            const int mnz = wave_min_i(act ? st.iz : big);
-            const int mxx = wave_max_i(act ? st.ix : -1), mxy = wave_max_i(act ? st.iy : -1);
-            const int mxz = wave_max_i(act ? st.iz : -1);
-            if (lane == 0) {
-                s_bb[par][w][0] = mnx; s_bb[par][w][1] = mny; s_bb[par][w][2] = mnz;
-                s_bb[par][w][3] = mxx; s_bb[par][w][4] = mxy; s_bb[par][w][5] = mxz;
+            if (am != 0ull) {
+                const int lf = __builtin_ctzll(am), ll = 63 - __builtin_clzll(am);
+                const int fx0 = __builtin_amdgcn_readlane(st.ix, lf), lx0 = __builtin_amdgcn_readlane(st.ix, ll);
+                const int fy0 = __builtin_amdgcn_readlane(st.iy, lf), ly0 = __builtin_amdgcn_readlane(st.iy, ll);
+                const int fz0 = __builtin_amdgcn_readlane(st.iz, lf), lz0 = __builtin_amdgcn_readlane(st.iz, ll);
+                if (lane == 0) {
+                    s_bb[par][w][0] = min(fx0, lx0); s_bb[par][w][1] = min(fy0, ly0); s_bb[par][w][2] = min(fz0, lz0);
+                    s_bb[par][w][3] = max(fx0, lx0); s_bb[par][w][4] = max(fy0, ly0); s_bb[par][w][5] = max(fz0, lz0);
+                }
             }
         }
         __syncthreads();
@@ -996,24 +1104,6 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
             }
         }
         __syncthreads();
-    }
-    if (pose_acc && ray_ok) {
-        double r[6];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            r[a] = wave_sum(gsum[a]);
-            r[3 + a] = wave_sum(gssum[a]);
-        }
-        if (lane == 0) {
-            double *pa = pose_acc + (size_t)kPoseAcc * fr.pose;
-            // dL/dt = sum g;  dL/dR = sum g (s dir)^T, dir = (sx, 0, cz)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                atomicAdd(pa + a, r[a]);
-                atomicAdd(pa + 3 + 3 * a + 0, r[3 + a] * ray.dirx);
-                atomicAdd(pa + 3 + 3 * a + 2, r[3 + a] * ray.dirz);
-            }
-        }
     }
 }
 
@@ -1387,7 +1477,7 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 #define DUS_BWD_LAUNCH(CH, SPK, FUSED)                                                          \
     hipLaunchKernelGGL((k_backward<CH, SPK, FUSED>), dim3(grid), dim3(64), 0, st, v, p, t,      \
-                       poses, gsrc, target, zbar, loss, xcd_group)
+                       poses, gsrc, target, zbar, pose_acc, loss, xcd_group)
 
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
@@ -1415,18 +1505,18 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
         return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || (!gZ && !pose_acc)) return e;
+    if (e != hipSuccess || !gZ) return e;
     int blocks = 0;
     for (int f = 0; f < t.n; ++f) blocks += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
     switch (scatter_rays) {
     case 2:
-        hipLaunchKernelGGL((k_scatter<2>), dim3(blocks), dim3(128), 0, st, v, t, poses, zbar, gZ, pose_acc, xcd_group);
+        hipLaunchKernelGGL((k_scatter<2>), dim3(blocks), dim3(128), 0, st, v, t, poses, zbar, gZ, xcd_group);
         break;
     case 4:
-        hipLaunchKernelGGL((k_scatter<4>), dim3(blocks), dim3(256), 0, st, v, t, poses, zbar, gZ, pose_acc, xcd_group);
+        hipLaunchKernelGGL((k_scatter<4>), dim3(blocks), dim3(256), 0, st, v, t, poses, zbar, gZ, xcd_group);
         break;
     case 8:
-        hipLaunchKernelGGL((k_scatter<8>), dim3(blocks), dim3(512), 0, st, v, t, poses, zbar, gZ, pose_acc, xcd_group);
+        hipLaunchKernelGGL((k_scatter<8>), dim3(blocks), dim3(512), 0, st, v, t, poses, zbar, gZ, xcd_group);
         break;
     default:
         return hipErrorInvalidValue;

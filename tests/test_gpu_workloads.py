@@ -202,3 +202,49 @@ def test_edge_sizes():
             assert H.rel_l2(gZ.cpu().numpy(), rV) <= 1e-5
         for p in range(len(fans)):
             assert np.all(np.abs(gp.cpu().numpy()[p] - rp[p]) <= 1e-5 * np.linalg.norm(rp[p]) + 1e-30)
+
+
+def test_registration_loop():
+    """Pose-only fused steps under a graph give the same pose gradient as the
+    separate forward / MSE / adjoint calls, and Adam on the poses reduces the
+    loss (signed-coefficient physics, small offsets)."""
+    import math
+
+    from paper_2508_06768_amd.registration import register
+    from paper_2508_06768_amd.render import FusedStep, Geometry, render, render_backward
+    rng = np.random.default_rng(5)
+    n = 96
+    Z = synth.brain_volume(77, n, 1.0, semi_range=(4.0, 18.0))
+    ph = synth.PhysicsSpec(refl_mode=1, speckle_on=True, blur_on=True, seed=3)
+    fans = [synth.FanSpec(64, 320, math.radians(60), 0.25, 0.0, p) for p in range(4)]
+    gt = np.array([[47.5 + rng.uniform(-8, 8), 47.5 + rng.uniform(-8, 8), rng.uniform(0, 3),
+                    *rng.uniform(-0.15, 0.15, 3)] for _ in range(4)], dtype=np.float32)
+    init = (gt + np.concatenate([rng.uniform(-3, 3, (4, 3)),
+                                 rng.uniform(-math.radians(3), math.radians(3), (4, 3))], 1)).astype(np.float32)
+    geom = Geometry(Z.shape, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), fans, ph)
+    Zt = torch.from_numpy(Z).to(DEV)
+    T = render(Zt, torch.from_numpy(gt).to(DEV), geom).clone()
+    P = torch.from_numpy(init).to(DEV)
+    # one fused pose-only step vs the separate calls
+    step = FusedStep(geom, pose_only=True, zero_grad_z=False)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    gp = torch.empty((4, 6), device=DEV)
+    step.step(Zt, P, T, loss=loss, grad_pose=gp)
+    img = render(Zt, P, geom)
+    d = (img - T).double()
+    grad = torch.zeros_like(d)
+    ref_loss = 0.0
+    for p in range(4):
+        o0, o1 = int(geom.offsets[p]), int(geom.offsets[p + 1])
+        ref_loss += float((d[o0:o1] ** 2).mean())
+        grad[o0:o1] = 2 * d[o0:o1] / (o1 - o0)
+    _, gp_ref = render_backward(Zt, P, geom, grad.float(), want_Z=False)
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
+    np.testing.assert_allclose(gp.cpu().numpy(), gp_ref.cpu().numpy(), rtol=1e-4,
+                               atol=1e-5 * float(gp_ref.abs().max()))
+    step.close()
+    res = register(Zt, geom, T, P, steps=80, lr_t=0.2, lr_w=math.radians(0.2))
+    print("registration loss", res.loss_history[0], "->", res.loss_history[-1], "steps/s", res.steps_per_s,
+          flush=True)
+    assert res.loss_history[-1] < 0.5 * res.loss_history[0]
