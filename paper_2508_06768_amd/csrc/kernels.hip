@@ -698,19 +698,25 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             gather_tile<C, true, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z);
         if (SPK) speckle_fill<T>(p, t0, j, fr.speckle_id, lane, s_xig, s_xir);
         __syncthreads();
-        // dL/de (or the target for the fused loss) staged through LDS
-#pragma unroll 1
+        // dL/de (or the target for the fused loss) staged through LDS: the C
+        // global loads are issued together, then the per-pixel gains
+        // (speckle, post-hoc attenuation) are applied in place
+#pragma unroll
         for (int m = 0; m < C; ++m) {
             const int i = m * 64 + lane;
             const int k = t0 + i;
-            float gv = 0.0f, gain = 1.0f;
-            if (k < S) {
-                if (SPK || p.atten == 1) gain = pixel_gain<SPK>(p, k, i, S, t0, postc, s_xig, s_xir);
-                if (FUSED) gv = target[obase + k];
-                else gv = gsrc[obase + k] * gain;
+            s_eb[pad4(i)] = (k < S) ? (FUSED ? target[obase + k] : gsrc[obase + k]) : 0.0f;
+        }
+        {
+            const bool has_gain = SPK || p.atten == 1;
+#pragma unroll 1
+            for (int m = 0; m < C; ++m) {
+                const int i = m * 64 + lane;
+                const int k = t0 + i;
+                const float gain = (has_gain && k < S) ? pixel_gain<SPK>(p, k, i, S, t0, postc, s_xig, s_xir) : 1.0f;
+                if (FUSED) s_gain[pad4(i)] = gain;
+                else s_eb[pad4(i)] *= gain;
             }
-            s_eb[pad4(i)] = gv;
-            if (FUSED) s_gain[pad4(i)] = gain;
         }
         __syncthreads();
 
