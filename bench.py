@@ -30,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_hbm_traffic_64x256x1024.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2508_06768_amd", "csrc", "kernels.hip")
+CALIB_BYTES = 512 << 20
 
 
 def log(*a):
@@ -47,6 +50,29 @@ def timed(fn, reps, stream_events):
     stop.record()
     stop.synchronize()
     return start.elapsed_time(stop) / reps
+
+
+def measured_traffic():
+    """HBM bytes per adjoint launch from the committed rocprofv3 counter
+    summary, or None when the kernel source has changed since the counters
+    were taken (the summary records the SHA-256 of the kernel source)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.lstrip().startswith("- `"):
+            k, v = line.split(":", 1)
+            fields[k.strip(" -`")] = v.strip(" `")
+    if fields.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(case, budget_s: float):
@@ -90,6 +116,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default="", help="reuse / store the tuned schedule in this JSON file")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also launch a plain device copy of 512 MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this renderer build has no multi-GPU path "
@@ -136,6 +164,7 @@ def main():
     log("bench: warmup done")
     t0 = time.perf_counter()
     ms = timed(fused, args.steps, ev)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     value = N / (ms * 1e-3)
     log(f"bench: fused batched step {ms:.3f} ms ({value:.3e} ray-samples/s)")
@@ -147,18 +176,27 @@ def main():
     log(f"bench: forward batched {ms_fwd:.3f} ms")
 
     # plain form: one launch sequence per pose, no graph
-    plain_ms = None
+    plain_ms = plain_fwd_ms = None
     if not args.no_plain:
         singles = []
         for p in range(B):
             g1 = Geometry(case.Z.shape, case.spacing, case.origin, [case.fans[p]], case.phys)
             s1 = FusedStep(g1, zero_grad_z=False, graph=False)
-            singles.append((s1, poses[p:p + 1].contiguous(), target[geom.offsets[p]:geom.offsets[p + 1]]))
+            singles.append((s1, poses[p:p + 1].contiguous(), target[geom.offsets[p]:geom.offsets[p + 1]], g1,
+                            out[geom.offsets[p]:geom.offsets[p + 1]], g1.workspace(False, dev)))
         gp1 = torch.empty((1, 6), device=dev)
+
+        def plain_fwd():
+            for _, p1, _, g1, o1, w1 in singles:
+                render(Z, p1, g1, out=o1, ws=w1)
+
+        plain_fwd()
+        plain_fwd_ms = timed(plain_fwd, max(2, args.steps // 4), ev)
+        log(f"bench: plain per-pose forward {plain_fwd_ms:.3f} ms")
 
         def plain():
             gZ.zero_()
-            for s1, p1, t1 in singles:
+            for s1, p1, t1, *_ in singles:
                 s1.step(Z, p1, t1, loss=loss, grad_Z=gZ, grad_pose=gp1)
 
         plain()
@@ -189,6 +227,14 @@ def main():
     dom = "adjoint" if ms_k_bwd >= ms_k_fwd else "forward"
     log(f"bench: kernels {json.dumps(kern)} footprint voxels {vfp}")
 
+    if args.calib_copy:
+        src = torch.empty(CALIB_BYTES // 4, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {CALIB_BYTES} bytes done")
+
     cpu = None
     if not args.no_cpu:
         log("bench: timing the FP64 CPU oracle")
@@ -215,6 +261,8 @@ def main():
         },
         "forward_batched": {"ms": ms_fwd, "value": N / (ms_fwd * 1e-3)},
         "plain_per_pose": None if plain_ms is None else {"ms": plain_ms, "value": N / (plain_ms * 1e-3)},
+        "plain_forward_per_pose": (None if plain_fwd_ms is None
+                                   else {"ms": plain_fwd_ms, "value": N / (plain_fwd_ms * 1e-3)}),
         "kernels": kern,
         "roofline": {
             "bound": "hbm",
@@ -223,7 +271,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": kern[dom]["GBs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic() if dom == "adjoint" else None,
         },
         "schedule": step.get_schedule(),
         "autotune_trials": None if tune is None else tune.get("trials"),

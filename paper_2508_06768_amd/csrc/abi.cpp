@@ -163,6 +163,7 @@ std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses)
     for (int i = 0; i < n_poses; ++i)
         if (fans[i].n_rays > 0 && fans[i].n_samples > 0) order.push_back(i);
     std::vector<dus::FanTable> out;
+    int64_t carries = 0;    // tile-carry records of all tables before this fan
     for (size_t g0 = 0; g0 < order.size(); g0 += dus::kMaxFans) {
         std::vector<int> grp(order.begin() + g0, order.begin() + std::min(order.size(), g0 + dus::kMaxFans));
         std::stable_sort(grp.begin(), grp.end(),
@@ -185,6 +186,8 @@ std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses)
             r.blk_begin = blks;
             r.pose = grp[q];
             r.pivot_begin = pivot_begin[grp[q]];
+            r.carry_begin = (int32_t)carries;
+            carries += dus::carry_records(f.n_rays, f.n_samples);
             rays += f.n_rays;
             blks += ((f.n_samples + 63) / 64) * ((f.n_rays + 63) / 64);
         }
@@ -204,6 +207,8 @@ struct WsLayout {
     size_t acc = 0, acc_bytes = 0;     // pose accumulators
     size_t zb = 0, zb_bytes = 0;       // dL/dZ per sample (adjoint)
     size_t part = 0, part_bytes = 0;   // loss partials (plan step)
+    size_t car = 0, car_bytes = 0;     // tile carries, 4 doubles per record (plan step)
+    size_t cex = 0, cex_bytes = 0;     // tile-carry exponents, one int32 per record
     size_t total = 0;
 };
 
@@ -244,6 +249,16 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         L.part = off;
         L.part_bytes = std::max<size_t>(n, 1) * sizeof(double);
         off = align_up(off + L.part_bytes);
+        size_t rec = 0;
+        for (int32_t i = 0; i < n_poses; ++i)
+            if (fans[i].n_rays > 0 && fans[i].n_samples > 0)
+                rec += (size_t)dus::carry_records(fans[i].n_rays, fans[i].n_samples);
+        L.car = off;
+        L.car_bytes = std::max<size_t>(rec, 1) * 4 * sizeof(double);
+        off = align_up(off + L.car_bytes);
+        L.cex = off;
+        L.cex_bytes = std::max<size_t>(rec, 1) * sizeof(int32_t);
+        off = align_up(off + L.cex_bytes);
     }
     L.total = off;
     return L;
@@ -298,10 +313,11 @@ int make_sched(const dus_schedule *sc, Sched &n)
 
 int enqueue_forward(const Sched &sc, const dus::VolArgs &va, const dus::PhysArgs &pa,
                     const std::vector<dus::FanTable> &tabs, const float *poses, float *out,
-                    float *min_pivot, hipStream_t st)
+                    float *min_pivot, hipStream_t st, double *carry = nullptr, int32_t *carry_exp = nullptr)
 {
     for (const auto &t : tabs)
-        DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, out, min_pivot, 0, st),
+        DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, out, min_pivot, 0, carry,
+                                    carry_exp, st),
                 "forward kernel launch");
     return DUS_OK;
 }
@@ -406,7 +422,7 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
         for (const auto &t : tabs)
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, src, nullptr,
                                          reinterpret_cast<float *>((char *)ws + L.zb), grad_Z,
-                                         grad_pose ? acc : nullptr, nullptr, st),
+                                         grad_pose ? acc : nullptr, nullptr, nullptr, nullptr, st),
                     "adjoint kernel launch");
     }
     if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel launch");
@@ -562,12 +578,15 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     if (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z))
         DUS_HIP(dus::launch_zero_f32(gZ, (int64_t)p->vol.nx * p->vol.ny * p->vol.nz, st), "zero kernel");
     const Sched &sc = p->sched;
+    // the forward records its tile carries; the adjoint starts from them
+    double *car = reinterpret_cast<double *>((char *)ws + p->ws.car);
+    int32_t *cex = reinterpret_cast<int32_t *>((char *)ws + p->ws.cex);
     if (p->phys.blur_on) {
         float *pre = reinterpret_cast<float *>((char *)ws + p->ws.pre);
         float *res = reinterpret_cast<float *>((char *)ws + p->ws.res);
         float *eb = reinterpret_cast<float *>((char *)ws + p->ws.eb);
         int s;
-        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, pre, nullptr, st)) != DUS_OK) return s;
+        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, pre, nullptr, st, car, cex)) != DUS_OK) return s;
         for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, eb, loss ? part + n_part : nullptr, st),
                     "blur/loss kernel");
@@ -576,16 +595,17 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         if (gZ || grad_pose)
             for (const auto &t : p->tabs)
                 DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, eb, nullptr, zbar, gZ,
-                                             grad_pose ? acc : nullptr, nullptr, st),
+                                             grad_pose ? acc : nullptr, nullptr, car, cex, st),
                         "adjoint kernel");
     } else {
         if (bmode) {
             int s;
-            if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st)) != DUS_OK) return s;
+            if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st, car, cex)) != DUS_OK) return s;
         }
         for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, nullptr, target, zbar, gZ,
-                                         grad_pose ? acc : nullptr, loss ? part + n_part : nullptr, st),
+                                         grad_pose ? acc : nullptr, loss ? part + n_part : nullptr,
+                                         bmode ? car : nullptr, bmode ? cex : nullptr, st),
                     "fused adjoint kernel");
             n_part += t.total_rays;
         }

@@ -18,8 +18,21 @@ struct FanRec {
     int32_t blk_begin;      // first blur block of this fan
     int32_t pose;           // row of the poses array
     int32_t pivot_begin;    // pose-major index of this fan's first ray
+    int32_t carry_begin;    // first tile-carry record of this fan's first ray
+    int32_t pad_;
 };
-static_assert(sizeof(FanRec) == 48, "FanRec layout");
+static_assert(sizeof(FanRec) == 56, "FanRec layout");
+
+// Tile carries: the forward kernel records, at every 256-sample boundary of
+// a ray, the carried row vector and determinant (v0, v1, D) and the sample
+// before the boundary, renormalised by a power of two whose exponent is
+// stored relative to the previous boundary.  The adjoint then starts its
+// reverse sweep from these records instead of re-running the forward.
+constexpr int kCarryBlock = 256;
+inline int64_t carry_records(int32_t n_rays, int32_t n_samples)
+{
+    return (int64_t)n_rays * ((n_samples + kCarryBlock - 1) / kCarryBlock);
+}
 
 struct FanTable {
     int32_t n;              // fans in this launch
@@ -52,15 +65,18 @@ constexpr int kPoseAcc = 12;
 
 // Launch wrappers (kernels.hip).  All enqueue on `st` and return the HIP
 // error of the launch.
+// carry / carry_exp: optional tile-carry records (4 doubles / 1 int each)
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out,
-                          float *min_pivot, int pivot_base, hipStream_t st);
+                          float *min_pivot, int pivot_base, double *carry, int32_t *carry_exp,
+                          hipStream_t st);
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
 // the fused form (target given) loss receives one partial per ray
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
-                           double *pose_acc, double *loss, hipStream_t st);
+                           double *pose_acc, double *loss, const double *carry,
+                           const int32_t *carry_exp, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st);
 // image = B pre (optional), ebar = B^T (2 (image - target) / P); loss

@@ -359,12 +359,13 @@ __device__ __forceinline__ float posthoc_coef(const PhysArgs &p, float ds)
 
 // --------------------------------------------------------------------------
 // phase 1: gather samples [t0, t0+T) of a ray, interface rho of (k-1, k)
-// into s_rho[pad8(k - t0)]; optionally keep the samples in s_z.
+// into s_rho[pad8(k - t0)]; optionally keep the samples in s_z, and the
+// last sample of every 256-sample block in s_zc (tile carries).
 // --------------------------------------------------------------------------
 template <int C, bool KEEPZ, bool KEEPG = false>
 __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, int t0, int S,
                                             bool absm, int lane, double &zprev, double *s_rho,
-                                            double *s_z, float *s_g = nullptr)
+                                            double *s_z, float *s_g = nullptr, double *s_zc = nullptr)
 {
     constexpr int T = 64 * C;
     const int sxy = v.nx * v.ny;
@@ -382,6 +383,7 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
         if (k >= 1 && k < S) rho = iface_rho(zm, z, absm);
         s_rho[pad8(i)] = rho;
         if (KEEPZ) s_z[pad8(i)] = z;
+        if (s_zc && lane == 63 && (jj & 3) == 3) s_zc[jj >> 2] = z;
         if (KEEPG) {
             s_g[i] = (float)gu[0];
             s_g[T + i] = (float)gu[1];
@@ -491,10 +493,15 @@ template <int C, bool SPK>
 __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable tab,
                                                 const float *__restrict__ poses,
                                                 float *__restrict__ out, float *__restrict__ minpiv,
-                                                int pivot_base, int xgrp)
+                                                int pivot_base, double *__restrict__ carry,
+                                                int32_t *__restrict__ carry_exp, int xgrp)
 {
     constexpr int T = 64 * C;
+    static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
+    constexpr int NB = T / kCarryBlock;     // carry blocks per tile
+    constexpr int LB = kCarryBlock / C;     // lanes per carry block
     __shared__ double s_rho[T + T / 16];
+    __shared__ double s_zc[NB];
     __shared__ float s_pix[T + T / 32];
     __shared__ float s_xig[SPK ? T : 1];
     __shared__ float s_xir[SPK ? T / 4 + 8 : 1];
@@ -516,9 +523,13 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     double c0 = 0.0, c1 = 1.0, cD = 1.0, zprev = 0.0;
     double piv = 1e300;
     const bool want_piv = (minpiv != nullptr);
+    const long long crec = (long long)fr.carry_begin + (long long)j * ((S + kCarryBlock - 1) / kCarryBlock);
+    int first_rel = 0;      // exponent of this tile's carry relative to the previous record
 
     for (int t0 = 0; t0 < S; t0 += T) {
-        gather_tile<C, false>(v, ray, t0, S, absm, lane, zprev, s_rho, nullptr);
+        const double zstart = zprev;
+        gather_tile<C, false>(v, ray, t0, S, absm, lane, zprev, s_rho, nullptr, nullptr,
+                              carry ? s_zc : nullptr);
         if (SPK) speckle_fill<T>(p, t0, j, fr.speckle_id, lane, s_xig, s_xir);
         __syncthreads();
 
@@ -527,6 +538,29 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
         double qd, xd, td;
         chunk_product<C>(s_rho, base, t0, S, a2, sgn, Q, qd);
         scan_exclusive(lane, Q, qd, X, xd, Tot, td);
+        int e_last = 0;
+        if (carry) {
+            // state at the start of carry block m = lane / LB (lanes on a
+            // block boundary), renormalised; exponents relative to the
+            // previous block's
+            const int m = lane / LB;
+            const double u0 = fma(c0, X.a, c1 * X.c);
+            const double u1 = fma(c0, X.b, c1 * X.d);
+            const double uD = cD * xd;
+            const int e = (lane == 0) ? 0 : renorm_exp(u0, u1);
+            const int e_prev = __shfl_up(e, LB);
+            const int kb = t0 + m * kCarryBlock;
+            if ((lane % LB) == 0 && kb < S) {
+                const long long r = crec + kb / kCarryBlock;
+                double *q = carry + 4 * r;
+                q[0] = (lane == 0) ? c0 : ldexp(u0, -e);
+                q[1] = (lane == 0) ? c1 : ldexp(u1, -e);
+                q[2] = (lane == 0) ? cD : ldexp(uD, -2 * e);
+                q[3] = (m == 0) ? zstart : s_zc[m - 1];
+                carry_exp[r] = (m == 0) ? first_rel : e - e_prev;
+            }
+            e_last = lane_read(e, LB * (NB - 1));
+        }
         double v0 = fma(c0, X.a, c1 * X.c);
         double v1 = fma(c0, X.b, c1 * X.d);
         double D = cD * xd;
@@ -557,6 +591,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             c0 = ldexp(n0, -ex);
             c1 = ldexp(n1, -ex);
             cD = ldexp(nD, -2 * ex);
+            first_rel = ex - e_last;
         }
         __syncthreads();
 #pragma unroll 1
@@ -618,10 +653,14 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                                                  const float *__restrict__ target,
                                                  float *__restrict__ zbar,
                                                  double *__restrict__ pose_acc,
-                                                 double *__restrict__ loss_acc, int xgrp)
+                                                 double *__restrict__ loss_acc,
+                                                 const double *__restrict__ carry,
+                                                 const int32_t *__restrict__ carry_exp, int xgrp)
 {
     constexpr int T = 64 * C;
     constexpr int kMaxTiles = (DUS_MAX_SAMPLES + T - 1) / T;
+    static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
+    constexpr int NB = T / kCarryBlock;
     __shared__ float s_g[3 * T];     // dZ/du of every sample of the tile
     __shared__ double s_rho[T + T / 16];
     __shared__ double s_z[T + T / 16];
@@ -649,8 +688,31 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     const int ntiles = (S + T - 1) / T;
     const double inv_npix = 1.0 / ((double)fr.n_rays * (double)S);
 
-    // forward sweep: state at every tile start
-    {
+    if (carry) {
+        // tile starts from the forward kernel's carry records; the exponent
+        // of tile t relative to tile t - 1 sums those of its carry blocks
+        __shared__ int s_bexp[(DUS_MAX_SAMPLES + kCarryBlock - 1) / kCarryBlock];
+        const int nblk = (S + kCarryBlock - 1) / kCarryBlock;
+        const long long rb = (long long)fr.carry_begin + (long long)j * nblk;
+        for (int b = lane; b < nblk; b += 64) {
+            s_bexp[b] = carry_exp[rb + b];
+            if (b % NB == 0) {
+                const double *q = carry + 4 * (rb + b);
+                s_carry[b / NB][0] = q[0];
+                s_carry[b / NB][1] = q[1];
+                s_carry[b / NB][2] = q[2];
+                s_carry[b / NB][3] = q[3];
+            }
+        }
+        __syncthreads();
+        for (int t = 1 + lane; t < ntiles; t += 64) {
+            int e = 0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) e += s_bexp[(t - 1) * NB + 1 + q];
+            s_cexp[t] = e;
+        }
+    } else {
+        // forward sweep: state at every tile start
         double c0 = 0.0, c1 = 1.0, cD = 1.0, zprev = 0.0;
         for (int t = 0; t < ntiles; ++t) {
             if (lane == 0) {
@@ -1117,79 +1179,56 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
 // lateral blur (Sec. 2.4): per depth row k, a normalised Gaussian along the
 // ray index, sigma_k = s0 + (s1 - s0) k / (S - 1) rays, radius ceil(3 sigma)
 // decided in float32, edge replicate.  A block of 4 wavefronts takes 64 rays
-// x 64 depths; lanes run along depth (coalesced rows), the rows it needs
-// (with the blur halo) are staged once in LDS.
+// x 64 depths; lanes run along depth (coalesced 256-byte rows) and each
+// wavefront owns 16 consecutive rays.  A wavefront loads its rows plus the
+// halo of RM rays on either side straight into registers (all loads issued
+// before the first use) and keeps its depth's weights in registers, so no
+// LDS staging and no block barrier sits between the loads and the sums.
 //   MODE 0: out = B in            MODE 1: out = B^T in
 //   MODE 2: image = B in, out = 2 (image - target) / P, loss += |.|^2 / P
-//   MODE 3: MODE 2 followed by B^T on the residual, in one pass (halo 2R)
+// RM (4, 8, 16, 32) is a register bound on the radius: taps beyond a row's
+// own radius carry weight zero and leave the sums unchanged.
 // --------------------------------------------------------------------------
-constexpr int kBlurRays = 64;
+constexpr int kBlurRays = 64;      // rays per block
+constexpr int kBlurRows = 16;      // rays per wavefront
 
-// normalised weights w_|t| (t = 0..r) and tails sum_{t >= m} w_|t| of depth
-// row k; returns the radius (-1: identity row)
-__device__ __forceinline__ int blur_row(const PhysArgs &p, int S, int k, float *w, float *tail, int stride)
+// normalised weights w_t (t = 0..RM, zero beyond the row radius r) of depth
+// row k; returns r (-1: identity row, w_0 = 1)
+template <int RM>
+__device__ __forceinline__ int blur_weights(const PhysArgs &p, int S, int k, float (&w)[RM + 1])
 {
     const float frac = S > 1 ? __fdiv_rn((float)k, (float)(S - 1)) : 0.0f;
     const float d = __fsub_rn(p.s1, p.s0);
     const float sig = __fadd_rn(p.s0, __fmul_rn(d, frac));
-    if (!(sig >= 1e-3f)) return -1;
-    int r = (int)ceilf(__fmul_rn(3.0f, sig));
-    r = min(r, p.blur_rmax);
-    const float c = -0.5f / (sig * sig);
-    float tot = 1.0f;
-    for (int t = 1; t <= r; ++t) tot += 2.0f * expf(c * (float)(t * t));
-    const float inv = 1.0f / tot;
-    float acc = 0.0f;
-    for (int t = r; t >= 0; --t) {
-        const float wt = expf(c * (float)(t * t)) * inv;
-        w[t * stride] = wt;
-        acc += wt;
-        tail[t * stride] = acc;
+    if (!(sig >= 1e-3f)) {
+#pragma unroll
+        for (int t = 0; t <= RM; ++t) w[t] = (t == 0) ? 1.0f : 0.0f;
+        return -1;
     }
-    tail[(r + 1) * stride] = 0.0f;
+    int r = (int)ceilf(__fmul_rn(3.0f, sig));
+    r = min(r, min(p.blur_rmax, RM));
+    const float c = -0.5f / (sig * sig);
+    float e[RM + 1];
+    float tot = 1.0f;
+#pragma unroll
+    for (int t = 1; t <= RM; ++t) {
+        e[t] = (t <= r) ? expf(c * (float)(t * t)) : 0.0f;
+        if (t <= r) tot += 2.0f * e[t];
+    }
+    const float inv = 1.0f / tot;
+    w[0] = inv;
+#pragma unroll
+    for (int t = 1; t <= RM; ++t) w[t] = e[t] * inv;
     return r;
 }
 
-// blur of row j (0 <= j < n) from a tile whose row 0 is global row `base`
-// (rows outside [0, n) stored clamped)
-__device__ __forceinline__ float blur_at(const float *tile, int base, int j, int r, const float *s_w, int lane)
-{
-    float acc = 0.0f;
-    for (int t = -r; t <= r; ++t) acc = fmaf(s_w[(t < 0 ? -t : t) * 64 + lane], tile[(j + t - base) * 64 + lane], acc);
-    return acc;
-}
-
-// transpose of the blur at row i from a tile holding rows [base, ...) for
-// the rows q in [max(0, i - r), min(n - 1, i + r)]
-__device__ __forceinline__ float blur_t_at(const float *tile, int base, int i, int r, int n, const float *s_w,
-                                           const float *s_tail, int lane)
-{
-    const int lo = max(0, i - r), hi = min(n - 1, i + r);
-    float acc = 0.0f;
-    for (int q = lo; q <= hi; ++q) {
-        const int t = i - q;
-        float w = s_w[(t < 0 ? -t : t) * 64 + lane];
-        if (i == 0) w += s_tail[(q + 1) * 64 + lane];
-        if (i == n - 1) w += s_tail[(n - q) * 64 + lane];
-        acc = fmaf(w, tile[(q - base) * 64 + lane], acc);
-    }
-    return acc;
-}
-
-template <int MODE>
+template <int MODE, int RM>
 __global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const float *__restrict__ in,
                                               const float *__restrict__ target, float *__restrict__ out,
                                               float *__restrict__ image, double *__restrict__ loss_acc)
 {
-    extern __shared__ float smem[];
-    const int R = p.blur_rmax;
-    float *s_w = smem;                                   // (R + 1) x 64
-    float *s_tail = s_w + (R + 1) * 64;                  // (R + 2) x 64
-    int *s_r = reinterpret_cast<int *>(s_tail + (R + 2) * 64);   // 64
-    float *tileA = reinterpret_cast<float *>(s_r + 64);  // input rows
-    const int halo = (MODE == 3) ? 2 * R : R;
-    float *tileB = tileA + (kBlurRays + 2 * halo) * 64;  // residual rows (MODE 3)
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    constexpr int W = kBlurRows + 2 * RM;      // window rows j0 - RM .. j0 + 16 + RM - 1
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int b = blockIdx.x;
     const int fi = find_blur_fan(tab, b);
     const FanRec fr = tab.f[fi];
@@ -1198,87 +1237,74 @@ __global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const fl
     const int lb = b - fr.blk_begin;
     const int kb = lb % nkb, jb = lb / nkb;
     const int k = kb * 64 + lane;
-    const bool active = k < S;
-    if (w == 0) s_r[lane] = active ? blur_row(p, S, k, s_w + lane, s_tail + lane, 64) : -1;
-    const int j0 = jb * kBlurRays, j1 = min(n, j0 + kBlurRays);
+    const int j0 = jb * kBlurRays + wv * kBlurRows;
+    const bool active = (k < S) && (j0 < n);
     const long long col = fr.out_offset + k;
-    // stage input rows [j0 - halo, j1 + halo), clamped for the forward blur
-    const int baseA = j0 - halo, rowsA = (j1 - j0) + 2 * halo;
-    for (int q = w; q < rowsA; q += 4) {
-        const int g = baseA + q;
-        float val = 0.0f;
-        if (active) {
-            if (MODE == 1) {
-                if (g >= 0 && g < n) val = in[col + (long long)g * S];
-            } else {
-                val = in[col + (long long)min(max(g, 0), n - 1) * S];
-            }
-        }
-        tileA[q * 64 + lane] = val;
-    }
-    __syncthreads();
-    const int r = s_r[lane];
     const double inv_npix = 1.0 / ((double)n * (double)S);
     double lsum = 0.0;
-    if (MODE == 0 || MODE == 1 || MODE == 2) {
-        for (int j = j0 + w; j < j1; j += 4) {
-            if (!active) continue;
-            float acc;
-            if (r < 0) acc = tileA[(j - baseA) * 64 + lane];
-            else if (MODE == 1) acc = blur_t_at(tileA, baseA, j, r, n, s_w, s_tail, lane);
-            else acc = blur_at(tileA, baseA, j, r, s_w, lane);
-            const long long o = col + (long long)j * S;
+    if (active) {
+        float x[W];
+#pragma unroll
+        for (int m = 0; m < W; ++m) {
+            const int g = j0 - RM + m;
+            if (MODE == 1)
+                x[m] = (g >= 0 && g < n) ? in[col + (long long)g * S] : 0.0f;
+            else
+                x[m] = in[col + (long long)min(max(g, 0), n - 1) * S];
+        }
+        float tg[MODE == 2 ? kBlurRows : 1];
+        if (MODE == 2) {
+#pragma unroll
+            for (int o = 0; o < kBlurRows; ++o)
+                tg[o] = (j0 + o < n) ? target[col + (long long)(j0 + o) * S] : 0.0f;
+        }
+        float w[RM + 1];
+        const int r = blur_weights<RM>(p, S, k, w);
+        // transpose at the edge rows 0 and n-1: the replicated taps fold back
+        // onto the edge, weight tail_m = sum_{t >= m} w_t for the tap |t| + 1
+        float tl[RM + 2];
+        if (MODE == 1) {
+            float acc = 0.0f;
+            tl[RM + 1] = 0.0f;
+#pragma unroll
+            for (int t = RM; t >= 0; --t) {
+                if (t <= r) acc += w[t];
+                tl[t] = (t <= r) ? acc : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < kBlurRows; ++o) {
+            const int j = j0 + o;
+            if (j >= n) break;
+            float acc = 0.0f;
+#pragma unroll
+            for (int t = -RM; t <= RM; ++t) acc = fmaf(w[t < 0 ? -t : t], x[o + RM + t], acc);
+            if (MODE == 1 && (j == 0 || j == n - 1)) {
+                const float mult = (j == 0 && j == n - 1) ? 2.0f : 1.0f;
+                float e = 0.0f;
+#pragma unroll
+                for (int t = -RM; t <= RM; ++t) e = fmaf(tl[(t < 0 ? -t : t) + 1], x[o + RM + t], e);
+                acc = fmaf(mult, e, acc);
+            }
+            const long long oidx = col + (long long)j * S;
             if (MODE == 2) {
-                const double dd = (double)acc - (double)target[o];
-                if (image) image[o] = acc;
-                out[o] = (float)(2.0 * dd * inv_npix);
+                const double dd = (double)acc - (double)tg[o];
+                if (image) image[oidx] = acc;
+                out[oidx] = (float)(2.0 * dd * inv_npix);
                 lsum += dd * dd * inv_npix;
             } else {
-                out[o] = acc;
+                out[oidx] = acc;
             }
-        }
-    } else {
-        // residual rows [j0 - R, j1 + R) clipped to [0, n)
-        const int baseB = j0 - R, rowsB = (j1 - j0) + 2 * R;
-        for (int q = w; q < rowsB; q += 4) {
-            const int j = baseB + q;
-            float res = 0.0f;
-            if (active && j >= 0 && j < n) {
-                const float I = (r < 0) ? tileA[(j - baseA) * 64 + lane] : blur_at(tileA, baseA, j, r, s_w, lane);
-                const long long o = col + (long long)j * S;
-                const double dd = (double)I - (double)target[o];
-                res = (float)(2.0 * dd * inv_npix);
-                if (j >= j0 && j < j1) {
-                    lsum += dd * dd * inv_npix;
-                    if (image) image[o] = I;
-                }
-            }
-            tileB[q * 64 + lane] = res;
-        }
-        __syncthreads();
-        for (int i = j0 + w; i < j1; i += 4) {
-            if (!active) continue;
-            const float e = (r < 0) ? tileB[(i - baseB) * 64 + lane]
-                                    : blur_t_at(tileB, baseB, i, r, n, s_w, s_tail, lane);
-            out[col + (long long)i * S] = e;
         }
     }
-    if ((MODE == 2 || MODE == 3) && loss_acc) {
+    if (MODE == 2 && loss_acc) {
         // one partial per block, summed by k_sum_f64 (no contended atomics)
         __shared__ double s_part[4];
         lsum = wave_sum(lsum);
-        if (lane == 0) s_part[w] = lsum;
+        if (lane == 0) s_part[wv] = lsum;
         __syncthreads();
         if (tid == 0) loss_acc[b] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
     }
-}
-
-inline size_t blur_smem(int mode, int R)
-{
-    const int halo = (mode == 3) ? 2 * R : R;
-    size_t f = (size_t)(R + 1) * 64 + (size_t)(R + 2) * 64 + 64 + (size_t)(kBlurRays + 2 * halo) * 64;
-    if (mode == 3) f += (size_t)(kBlurRays + 2 * R) * 64;
-    return f * 4;
 }
 
 // --------------------------------------------------------------------------
@@ -1459,15 +1485,15 @@ inline int grid_for(long long n, int block)
     case CH:                                                                                   \
         if (p.speckle)                                                                         \
             hipLaunchKernelGGL((k_forward<CH, true>), dim3(grid), dim3(64), 0, st, v, p, t,    \
-                               poses, out, min_pivot, pivot_base, xcd_group);                  \
+                               poses, out, min_pivot, pivot_base, carry, carry_exp, xcd_group); \
         else                                                                                   \
             hipLaunchKernelGGL((k_forward<CH, false>), dim3(grid), dim3(64), 0, st, v, p, t,   \
-                               poses, out, min_pivot, pivot_base, xcd_group);                  \
+                               poses, out, min_pivot, pivot_base, carry, carry_exp, xcd_group); \
         break;
 
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out, float *min_pivot,
-                          int pivot_base, hipStream_t st)
+                          int pivot_base, double *carry, int32_t *carry_exp, hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
@@ -1483,7 +1509,7 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 #define DUS_BWD_LAUNCH(CH, SPK, FUSED)                                                          \
     hipLaunchKernelGGL((k_backward<CH, SPK, FUSED>), dim3(grid), dim3(64), 0, st, v, p, t,      \
-                       poses, gsrc, target, zbar, pose_acc, loss, xcd_group)
+                       poses, gsrc, target, zbar, pose_acc, loss, carry, carry_exp, xcd_group)
 
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
@@ -1499,7 +1525,8 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
-                           double *pose_acc, double *loss, hipStream_t st)
+                           double *pose_acc, double *loss, const double *carry,
+                           const int32_t *carry_exp, hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
@@ -1530,18 +1557,29 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
     return hipGetLastError();
 }
 
+#define DUS_BLUR_LAUNCH(MODE, TGT, IMG, LOSS)                                                       \
+    do {                                                                                           \
+        if (R <= 4)                                                                                \
+            hipLaunchKernelGGL((k_blur<MODE, 4>), dim3(grid), dim3(256), 0, st, p, t, in, TGT, out, IMG, LOSS);  \
+        else if (R <= 8)                                                                           \
+            hipLaunchKernelGGL((k_blur<MODE, 8>), dim3(grid), dim3(256), 0, st, p, t, in, TGT, out, IMG, LOSS);  \
+        else if (R <= 16)                                                                          \
+            hipLaunchKernelGGL((k_blur<MODE, 16>), dim3(grid), dim3(256), 0, st, p, t, in, TGT, out, IMG, LOSS); \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_blur<MODE, 32>), dim3(grid), dim3(256), 0, st, p, t, in, TGT, out, IMG, LOSS); \
+    } while (0)
+
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st)
 {
     const int grid = t.total_blur_blocks;
     if (grid <= 0) return hipSuccess;
     const int R = p.blur_rmax;
+    if (R > DUS_MAX_BLUR_RADIUS) return hipErrorInvalidValue;
     if (transpose)
-        hipLaunchKernelGGL((k_blur<1>), dim3(grid), dim3(256), blur_smem(1, R), st, p, t, in, nullptr, out,
-                           nullptr, nullptr);
+        DUS_BLUR_LAUNCH(1, nullptr, nullptr, nullptr);
     else
-        hipLaunchKernelGGL((k_blur<0>), dim3(grid), dim3(256), blur_smem(0, R), st, p, t, in, nullptr, out,
-                           nullptr, nullptr);
+        DUS_BLUR_LAUNCH(0, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -1552,8 +1590,12 @@ hipError_t launch_blur_residual(const PhysArgs &p, const FanTable &t, const floa
     const int grid = t.total_blur_blocks;
     if (grid <= 0) return hipSuccess;
     const int R = p.blur_rmax;
-    hipLaunchKernelGGL((k_blur<2>), dim3(grid), dim3(256), blur_smem(2, R), st, p, t, pre, target, resid, image,
-                       loss);
+    if (R > DUS_MAX_BLUR_RADIUS) return hipErrorInvalidValue;
+    {
+        const float *in = pre;
+        float *out = resid;
+        DUS_BLUR_LAUNCH(2, target, image, loss);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_blur(true, p, t, resid, ebar, st);
