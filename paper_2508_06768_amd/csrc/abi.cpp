@@ -40,7 +40,7 @@ bool finite_f(float x) { return isfinite(x) != 0; }
 constexpr int kDefaultFwdChunk = 8;
 constexpr int kDefaultBwdChunk = 4;
 constexpr int kDefaultXcdGroup = 16;
-constexpr int kDefaultScatterRays = 4;
+constexpr int kDefaultScatterRays = 8;
 
 int check_volume(const dus_volume *v)
 {
@@ -209,6 +209,7 @@ struct WsLayout {
     size_t part = 0, part_bytes = 0;   // loss partials (plan step)
     size_t car = 0, car_bytes = 0;     // tile carries, 4 doubles per record (plan step)
     size_t cex = 0, cex_bytes = 0;     // tile-carry exponents, one int32 per record
+    size_t gain = 0, gain_bytes = 0;   // per-pixel gains recorded by the forward (plan step)
     size_t total = 0;
 };
 
@@ -259,6 +260,11 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         L.cex = off;
         L.cex_bytes = std::max<size_t>(rec, 1) * sizeof(int32_t);
         off = align_up(off + L.cex_bytes);
+        if (p->speckle_on || p->atten_mode == DUS_ATTEN_POST_HOC) {
+            L.gain = off;
+            L.gain_bytes = img;
+            off = align_up(off + img);
+        }
     }
     L.total = off;
     return L;
@@ -313,11 +319,12 @@ int make_sched(const dus_schedule *sc, Sched &n)
 
 int enqueue_forward(const Sched &sc, const dus::VolArgs &va, const dus::PhysArgs &pa,
                     const std::vector<dus::FanTable> &tabs, const float *poses, float *out,
-                    float *min_pivot, hipStream_t st, double *carry = nullptr, int32_t *carry_exp = nullptr)
+                    float *min_pivot, hipStream_t st, double *carry = nullptr, int32_t *carry_exp = nullptr,
+                    float *gain = nullptr)
 {
     for (const auto &t : tabs)
         DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, out, min_pivot, 0, carry,
-                                    carry_exp, st),
+                                    carry_exp, gain, st),
                 "forward kernel launch");
     return DUS_OK;
 }
@@ -422,7 +429,7 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
         for (const auto &t : tabs)
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, src, nullptr,
                                          reinterpret_cast<float *>((char *)ws + L.zb), grad_Z,
-                                         grad_pose ? acc : nullptr, nullptr, nullptr, nullptr, st),
+                                         grad_pose ? acc : nullptr, nullptr, nullptr, nullptr, nullptr, st),
                     "adjoint kernel launch");
     }
     if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel launch");
@@ -581,12 +588,13 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     // the forward records its tile carries; the adjoint starts from them
     double *car = reinterpret_cast<double *>((char *)ws + p->ws.car);
     int32_t *cex = reinterpret_cast<int32_t *>((char *)ws + p->ws.cex);
+    float *gain = p->ws.gain_bytes ? reinterpret_cast<float *>((char *)ws + p->ws.gain) : nullptr;
     if (p->phys.blur_on) {
         float *pre = reinterpret_cast<float *>((char *)ws + p->ws.pre);
         float *res = reinterpret_cast<float *>((char *)ws + p->ws.res);
         float *eb = reinterpret_cast<float *>((char *)ws + p->ws.eb);
         int s;
-        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, pre, nullptr, st, car, cex)) != DUS_OK) return s;
+        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, pre, nullptr, st, car, cex, gain)) != DUS_OK) return s;
         for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, eb, loss ? part + n_part : nullptr, st),
                     "blur/loss kernel");
@@ -595,17 +603,17 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         if (gZ || grad_pose)
             for (const auto &t : p->tabs)
                 DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, eb, nullptr, zbar, gZ,
-                                             grad_pose ? acc : nullptr, nullptr, car, cex, st),
+                                             grad_pose ? acc : nullptr, nullptr, car, cex, gain, st),
                         "adjoint kernel");
     } else {
         if (bmode) {
             int s;
-            if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st, car, cex)) != DUS_OK) return s;
+            if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st, car, cex, gain)) != DUS_OK) return s;
         }
         for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, nullptr, target, zbar, gZ,
                                          grad_pose ? acc : nullptr, loss ? part + n_part : nullptr,
-                                         bmode ? car : nullptr, bmode ? cex : nullptr, st),
+                                         bmode ? car : nullptr, bmode ? cex : nullptr, bmode ? gain : nullptr, st),
                     "fused adjoint kernel");
             n_part += t.total_rays;
         }

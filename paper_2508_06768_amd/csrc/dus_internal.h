@@ -65,18 +65,19 @@ constexpr int kPoseAcc = 12;
 
 // Launch wrappers (kernels.hip).  All enqueue on `st` and return the HIP
 // error of the launch.
-// carry / carry_exp: optional tile-carry records (4 doubles / 1 int each)
+// carry / carry_exp: optional tile-carry records (4 doubles / 1 int each);
+// gain: optional per-pixel gain (speckle x post-hoc attenuation) output
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out,
                           float *min_pivot, int pivot_base, double *carry, int32_t *carry_exp,
-                          hipStream_t st);
+                          float *gain, hipStream_t st);
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
 // the fused form (target given) loss receives one partial per ray
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
                            double *pose_acc, double *loss, const double *carry,
-                           const int32_t *carry_exp, hipStream_t st);
+                           const int32_t *carry_exp, const float *gain, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st);
 // image = B pre (optional), ebar = B^T (2 (image - target) / P); loss

@@ -173,8 +173,11 @@ struct Ray {
     double r0, ds;
 };
 
+// wave_uniform: every lane of the wavefront traces the same ray (its
+// parameters are then kept in scalar registers)
 __device__ __forceinline__ void setup_ray(const VolArgs &v, const PhysArgs &p, const FanRec &fr,
-                                          const float *__restrict__ poses, int j, Ray &ray)
+                                          const float *__restrict__ poses, int j, Ray &ray,
+                                          bool wave_uniform = true)
 {
     const float *ps = poses + 6 * (size_t)fr.pose;
     const double t[3] = {ps[0], ps[1], ps[2]};
@@ -200,6 +203,7 @@ __device__ __forceinline__ void setup_ray(const VolArgs &v, const PhysArgs &p, c
     ray.dirz = cz;
     ray.r0 = r0;
     ray.ds = ds;
+    if (!wave_uniform) return;
     // every lane computed the same values: keep them in scalar registers
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -494,7 +498,8 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
                                                 const float *__restrict__ poses,
                                                 float *__restrict__ out, float *__restrict__ minpiv,
                                                 int pivot_base, double *__restrict__ carry,
-                                                int32_t *__restrict__ carry_exp, int xgrp)
+                                                int32_t *__restrict__ carry_exp,
+                                                float *__restrict__ gain_out, int xgrp)
 {
     constexpr int T = 64 * C;
     static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
@@ -600,8 +605,11 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             const int k = t0 + i;
             if (k < S) {
                 float pix = s_pix[pad4(i)];
-                if (SPK || p.atten == 1)
-                    pix *= pixel_gain<SPK>(p, k, i, S, t0, postc, s_xig, s_xir);
+                if (SPK || p.atten == 1) {
+                    const float gn = pixel_gain<SPK>(p, k, i, S, t0, postc, s_xig, s_xir);
+                    pix *= gn;
+                    if (gain_out) gain_out[obase + k] = gn;
+                }
                 out[obase + k] = pix;
             }
         }
@@ -655,7 +663,8 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                                                  double *__restrict__ pose_acc,
                                                  double *__restrict__ loss_acc,
                                                  const double *__restrict__ carry,
-                                                 const int32_t *__restrict__ carry_exp, int xgrp)
+                                                 const int32_t *__restrict__ carry_exp,
+                                                 const float *__restrict__ gain_in, int xgrp)
 {
     constexpr int T = 64 * C;
     constexpr int kMaxTiles = (DUS_MAX_SAMPLES + T - 1) / T;
@@ -744,7 +753,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
 
     // reverse sweep
     Adj lam{0.0, 0.0, 0.0};        // adjoint of the state at the current tile's end
-    double rbar_next = 0.0;        // rho-bar of the interface just after this tile
+    double rbar_next = 0.0;        // dL/dZ factor of the interface just after this tile
     double z_next = 0.0;           // first sample of the next tile
     double loss = 0.0;
     double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
@@ -763,13 +772,28 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         // dL/de (or the target for the fused loss) staged through LDS: the C
         // global loads are issued together, then the per-pixel gains
         // (speckle, post-hoc attenuation) are applied in place
+        if (gain_in) {
+            // gains recorded by the forward kernel
 #pragma unroll
-        for (int m = 0; m < C; ++m) {
-            const int i = m * 64 + lane;
-            const int k = t0 + i;
-            s_eb[pad4(i)] = (k < S) ? (FUSED ? target[obase + k] : gsrc[obase + k]) : 0.0f;
-        }
-        {
+            for (int m = 0; m < C; ++m) {
+                const int i = m * 64 + lane;
+                const int k = t0 + i;
+                const float x = (k < S) ? (FUSED ? target[obase + k] : gsrc[obase + k]) : 0.0f;
+                const float gn = (k < S) ? gain_in[obase + k] : 1.0f;
+                if (FUSED) {
+                    s_eb[pad4(i)] = x;
+                    s_gain[pad4(i)] = gn;
+                } else {
+                    s_eb[pad4(i)] = x * gn;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < C; ++m) {
+                const int i = m * 64 + lane;
+                const int k = t0 + i;
+                s_eb[pad4(i)] = (k < S) ? (FUSED ? target[obase + k] : gsrc[obase + k]) : 0.0f;
+            }
             const bool has_gain = SPK || p.atten == 1;
 #pragma unroll 1
             for (int m = 0; m < C; ++m) {
@@ -795,8 +819,9 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         const double v1s = fma(c0, X.b, c1 * X.d);
         const double Ds = cD * xd;
         Adj f{0.0, 0.0, 0.0};
+        const double w1s = rcp64(v1s);     // 1 / v1 at the chunk start
         {
-            double v0 = v0s, v1 = v1s, D = Ds;
+            double v0 = v0s, v1 = v1s, D = Ds, w1 = w1s;
             Mat QL{1.0, 0.0, 0.0, 1.0};
             double qdl = 1.0;
 #pragma unroll WALK_UNROLL
@@ -806,7 +831,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                     const double r = s_rho[pad8(base + i)];
                     const Map m = make_map(r, a2, sgn, true);
                     const double v1n = fma(v0, r, v1);
-                    const double w1 = rcp64(v1), w1p = rcp64(v1n);
+                    const double w1p = rcp64(v1n);
                     const double e = r * D * w1 * w1p;
                     double eb;
                     if (FUSED) {
@@ -831,6 +856,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                     const double v0n = fma(v0, m.m00, v1 * m.m10);
                     v0 = v0n;
                     v1 = v1n;
+                    w1 = w1p;
                     D *= m.det;
                 } else if (FUSED && k == 0) {
                     const double diff = -(double)s_eb[pad4(base + i)];
@@ -892,16 +918,16 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         //   lambda_{i+1} = (lambda_i - f_i) J_i^{-1},  det M_i = a^2 (1 - rho^2) > 0,
         // and gives dL/drho_i (adj_rbar).
         {
-            double v0 = v0s, v1 = v1s, D = Ds;
+            double v0 = v0s, v1 = v1s, D = Ds, w1 = w1s;
 #pragma unroll WALK_UNROLL
             for (int i = 0; i < C; ++i) {
                 const int k = t0 + base + i;
-                double rb = 0.0;
+                double qz = 0.0;
                 if (k >= 1 && k < S) {
                     const double r = s_rho[pad8(base + i)];
                     const Map m = make_map(r, a2, sgn, true);
                     const double v1n = fma(v0, r, v1);
-                    const double w1 = rcp64(v1), w1p = rcp64(v1n);
+                    const double w1p = rcp64(v1n);
                     const double e = r * D * w1 * w1p;
                     const double eb = s_eb[pad4(base + i)];
                     const double x0 = lc.l0 + eb * e * r * w1p;
@@ -913,14 +939,26 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                     const double dA = -2.0 * a2 * r * (1.0 + sgn);
                     const double dB = -a2 * sgn;
                     const double dE = -2.0 * a2 * r;
-                    rb = la.l0 * fma(v0, dA, v1 * dB) + la.l1 * v0 + eb * D * w1p * w1p + la.lD * D * dE;
+                    const double rb = la.l0 * fma(v0, dA, v1 * dB) + la.l1 * v0 + eb * D * w1p * w1p + la.lD * D * dE;
+                    // Eq. 1 on this interface (samples zl = Z_{k-1}, zr = Z_k):
+                    // d rho/d zr = s 2 zl / (zl + zr)^2, d rho/d zl = -s 2 zr / (zl + zr)^2,
+                    // s = sign(zr - zl) (ABS, sign(0) = 0) or 1; keep rb 2 s / (zl + zr)^2
+                    if (rb != 0.0) {
+                        const double zr = s_z[pad8(base + i)];
+                        const double zl = (base + i > 0) ? s_z[pad8(base + i - 1)] : zstart;
+                        const double zs = zl + zr;
+                        double sg = 1.0;
+                        if (absm) sg = (zr > zl) ? 1.0 : ((zr < zl) ? -1.0 : 0.0);
+                        qz = 2.0 * sg * rb * rcp64(zs * zs);
+                    }
                     lc = la;
                     const double v0n = fma(v0, m.m00, v1 * m.m10);
                     v0 = v0n;
                     v1 = v1n;
+                    w1 = w1p;
                     D *= m.det;
                 }
-                s_rho[pad8(base + i)] = rb;       // s_rho now holds rho-bar
+                s_rho[pad8(base + i)] = qz;       // s_rho now holds the interfaces' dL/dZ factors
             }
         }
         le = lstart;
@@ -941,26 +979,15 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             const int i = jj * 64 + lane;
             const int k = t0 + i;
             if (k >= S) continue;
-            double zb = 0.0;
-            const double zk = s_z[pad8(i)];
+            // sample k is the right end of interface k-1 and the left end of
+            // interface k
             const double zl = (i > 0) ? s_z[pad8(i - 1)] : zstart;
             const double zr = (i + 1 < T) ? s_z[pad8(i + 1)] : z_next;
-            const double rl = (k >= 1) ? s_rho[pad8(i)] : 0.0;                      // interface k-1
-            const double rr = (k + 1 < S) ? ((i + 1 < T) ? s_rho[pad8(i + 1)] : rbar_next) : 0.0;
-            if (rl != 0.0) {
-                // rho(zl, zk): d/dzk = sgn(zk - zl)^abs * 2 zl / (zl + zk)^2
-                const double s = zl + zk;
-                double dz = 2.0 * zl * rcp64(s * s);
-                if (absm) dz *= (zk > zl) ? 1.0 : ((zk < zl) ? -1.0 : 0.0);
-                zb = fma(rl, dz, zb);
-            }
-            if (rr != 0.0) {
-                // rho(zk, zr): d/dzk = -sgn(zr - zk)^abs * 2 zr / (zk + zr)^2
-                const double s = zk + zr;
-                double dz = -2.0 * zr * rcp64(s * s);
-                if (absm) dz *= (zr > zk) ? 1.0 : ((zr < zk) ? -1.0 : 0.0);
-                zb = fma(rr, dz, zb);
-            }
+            const double ql = (k >= 1) ? s_rho[pad8(i)] : 0.0;
+            const double qr = (k + 1 < S) ? ((i + 1 < T) ? s_rho[pad8(i + 1)] : rbar_next) : 0.0;
+            double zb = 0.0;
+            if (ql != 0.0) zb = ql * zl;
+            if (qr != 0.0) zb = fma(-qr, zr, zb);
             zbar[obase + k] = (float)zb;
             if (pose_acc && zb != 0.0) {
                 // dL/dp = zb dZ/du / h per axis (0 where the sample is clamped);
@@ -1008,42 +1035,61 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
 }
 
 // --------------------------------------------------------------------------
-// scatter of dL/dZ_k: trilinear weights into the volume gradient, and the
-// pose sums.  A workgroup takes RB neighbouring rays of one fan and walks
-// them together in groups of 64 depths.  The stencils of such a group fill a
-// small box of the volume (neighbouring rays of a fan overlap), so the group
-// accumulates into an LDS copy of that box with LDS atomics and then flushes
-// the box row by row: one global atomic per touched voxel, consecutive lanes
-// on consecutive x.  A group whose box does not fit falls back to per-sample
-// global atomics.
+// scatter of dL/dZ_k: trilinear weights into the volume gradient.  One
+// wavefront takes RB neighbouring rays of one fan (64/RB lanes per ray) and
+// walks them together in groups of 256/RB depths; every lane owns 4
+// consecutive depths of its ray.  A straight ray meets each cell once, so a
+// lane's consecutive samples in one cell form a run that it sums in
+// registers before touching memory.  The stencils of a group fill a small
+// box of the volume (neighbouring rays of a fan overlap); the runs go into an
+// LDS copy of that box with LDS atomics, and the box is then flushed with one
+// global atomic per touched voxel, consecutive lanes on consecutive x.  A
+// group whose box does not fit falls back to per-sample global atomics.
+//
+// The box holds 64-bit fixed point: integer LDS atomics run at the rate of
+// plain LDS stores on gfx950, FP32 LDS atomics several times slower.  A
+// group's scale 2^F follows from the largest exponent of its dL/dZ values so
+// that the sum of all its contributions stays below 2^62: every contribution
+// within 2^38 of the group's largest is kept more finely than an FP32 add
+// would keep it.
 // --------------------------------------------------------------------------
-constexpr int kBoxCap = 4096;      // floats of LDS box per workgroup
+constexpr int kScatterSpl = 4;     // consecutive depths per lane
 
-__device__ __forceinline__ int wave_min_i(int x)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d));
-    return x;
-}
+template <int RB>
+struct ScatterBox {
+    static constexpr int cap = RB == 2 ? 4096 : (RB == 4 ? 2048 : 1024);   // 64-bit entries
+};
 
-__device__ __forceinline__ int wave_max_i(int x)
+// largest biased FP32 exponent over the wavefront (bitwise, by ballots)
+__device__ __forceinline__ int wave_max_exp(int e)
 {
+    int m = 0;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d));
-    return x;
+    for (int b = 7; b >= 0; --b) {
+        const int c = m | (1 << b);
+        if (__ballot(e >= c) != 0ull) m = c;
+    }
+    return m;
 }
 
 template <int RB>
-__global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, const float *__restrict__ poses,
-                                                     const float *__restrict__ zbar, float *__restrict__ gZ,
-                                                     int xgrp)
+__global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const float *__restrict__ poses,
+                                                const float *__restrict__ zbar, float *__restrict__ gZ,
+                                                int xgrp)
 {
+    constexpr int LPR = 64 / RB;                 // lanes per ray
+    constexpr int G = LPR * kScatterSpl;         // depths per group
+    constexpr int CAP = ScatterBox<RB>::cap;
     // s_box is all zeros between groups: cleared once here, and every flush
     // clears the entries it reads
-    __shared__ float s_box[kBoxCap];
-    __shared__ int s_bb[2][RB][6];
-    const int tid = threadIdx.x;
-    const int w = tid >> 6, lane = tid & 63;
+    __shared__ unsigned long long s_box[CAP];
+    const int lane = threadIdx.x;
+    const int slot = lane / LPR, ll = lane % LPR;
+    // depth chunk of this lane, rotated by the ray slot: in one instruction
+    // the rays of the wavefront sit at different depths (>= 1 mm apart), so
+    // lanes of one LDS atomic rarely meet in one cell
+    constexpr int SH = LPR / RB;
+    const int ch = (ll + slot * SH) % LPR;
     // block -> (fan, first ray); each fan owns ceil(n_rays / RB) blocks
     const int b = remap_block(blockIdx.x, gridDim.x, xgrp);
     int fi = 0, acc = 0;
@@ -1053,121 +1099,168 @@ __global__ __launch_bounds__(64 * RB) void k_scatter(VolArgs v, FanTable tab, co
         acc += nb;
     }
     const FanRec fr = tab.f[fi];
-    const int j = (b - acc) * RB + w;
+    const int j = (b - acc) * RB + slot;
     const bool ray_ok = j < fr.n_rays;
     const int S = fr.n_samples;
     PhysArgs p{};
     p.atten = 2;
     Ray ray;
-    setup_ray(v, p, fr, poses, ray_ok ? j : 0, ray);
-    const long long obase = fr.out_offset + (long long)j * S;
+    setup_ray(v, p, fr, poses, ray_ok ? j : 0, ray, false);     // RB rays per wavefront
+    const float *zrow = zbar + fr.out_offset + (long long)(ray_ok ? j : 0) * S;
     const int sxy = v.nx * v.ny;
-    for (int t = tid; t < kBoxCap; t += 64 * RB) s_box[t] = 0.0f;
-    int par = 0;
+    for (int t = lane; t < CAP; t += 64) s_box[t] = 0ull;
     // dL/dZ of the next group is loaded one group ahead
-    float zb_next = (ray_ok && lane < S) ? zbar[obase + lane] : 0.0f;
-    for (int k0 = 0; k0 < S; k0 += 64) {
-        const int k = k0 + lane;
-        const float zbf = zb_next;
-        zb_next = (ray_ok && k + 64 < S) ? zbar[obase + k + 64] : 0.0f;
-        const bool act = (zbf != 0.0f);
-        Stencil st{0, 0, 0, 0, 0.0, 0.0, 0.0};
-        if (act) st = stencil_at(v, ray, k);
-        // bounding box of the group's stencil cells: cell coordinates are
-        // monotone along a straight ray, so the extremes sit at the first
-        // and the last active lane (double-buffered exchange between waves)
-        {
-            const unsigned long long am = __ballot(act);
-            if (lane == 0) {
-                if (am == 0ull) {
-                    s_bb[par][w][0] = s_bb[par][w][1] = s_bb[par][w][2] = 0x3fffffff;
-                    s_bb[par][w][3] = s_bb[par][w][4] = s_bb[par][w][5] = -1;
-                }
-            }
-            if (am != 0ull) {
-                const int lf = __builtin_ctzll(am), ll = 63 - __builtin_clzll(am);
-                const int fx0 = __builtin_amdgcn_readlane(st.ix, lf), lx0 = __builtin_amdgcn_readlane(st.ix, ll);
-                const int fy0 = __builtin_amdgcn_readlane(st.iy, lf), ly0 = __builtin_amdgcn_readlane(st.iy, ll);
-                const int fz0 = __builtin_amdgcn_readlane(st.iz, lf), lz0 = __builtin_amdgcn_readlane(st.iz, ll);
-                if (lane == 0) {
-                    s_bb[par][w][0] = min(fx0, lx0); s_bb[par][w][1] = min(fy0, ly0); s_bb[par][w][2] = min(fz0, lz0);
-                    s_bb[par][w][3] = max(fx0, lx0); s_bb[par][w][4] = max(fy0, ly0); s_bb[par][w][5] = max(fz0, lz0);
-                }
-            }
-        }
-        __syncthreads();
-        int ox = s_bb[par][0][0], oy = s_bb[par][0][1], oz = s_bb[par][0][2];
-        int ex = s_bb[par][0][3], ey = s_bb[par][0][4], ez = s_bb[par][0][5];
+    float zn[kScatterSpl];
 #pragma unroll
-        for (int q = 1; q < RB; ++q) {
-            ox = min(ox, s_bb[par][q][0]); oy = min(oy, s_bb[par][q][1]); oz = min(oz, s_bb[par][q][2]);
-            ex = max(ex, s_bb[par][q][3]); ey = max(ey, s_bb[par][q][4]); ez = max(ez, s_bb[par][q][5]);
+    for (int q = 0; q < kScatterSpl; ++q) {
+        const int k = ch * kScatterSpl + q;
+        zn[q] = (ray_ok && k < S) ? zrow[k] : 0.0f;
+    }
+    for (int k0 = 0; k0 < S; k0 += G) {
+        float zb[kScatterSpl];
+#pragma unroll
+        for (int q = 0; q < kScatterSpl; ++q) {
+            zb[q] = zn[q];
+            const int k = k0 + G + ch * kScatterSpl + q;
+            zn[q] = (ray_ok && k < S) ? zrow[k] : 0.0f;
         }
-        par ^= 1;
-        if (ex < 0) continue;  // nothing to scatter in this group (uniform)
+        Stencil st[kScatterSpl];
+        int qf = -1, ql = -1;
+#pragma unroll
+        for (int q = 0; q < kScatterSpl; ++q) {
+            st[q] = Stencil{0, 0, 0, 0, 0.0, 0.0, 0.0};
+            if (zb[q] != 0.0f) {
+                st[q] = stencil_at(v, ray, k0 + ch * kScatterSpl + q);
+                if (qf < 0) qf = q;
+                ql = q;
+            }
+        }
+        // bounding box of the group's cells: cell coordinates are monotone
+        // along a straight ray, so per ray the extremes sit at its first and
+        // last active sample (first and last active chunk)
+        int fx = 0, fy = 0, fz = 0, lx = 0, ly = 0, lz = 0;
+#pragma unroll
+        for (int q = 0; q < kScatterSpl; ++q) {
+            if (q == qf) { fx = st[q].ix; fy = st[q].iy; fz = st[q].iz; }
+            if (q == ql) { lx = st[q].ix; ly = st[q].iy; lz = st[q].iz; }
+        }
+        const unsigned long long am = __ballot(qf >= 0);
+        if (am == 0ull) continue;  // nothing to scatter in this group (uniform)
+        int ox = 0x3fffffff, oy = 0x3fffffff, oz = 0x3fffffff, ex = -1, ey = -1, ez = -1;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            constexpr unsigned long long msk = (1ull << LPR) - 1;
+            const unsigned long long m = (am >> (r * LPR)) & msk;
+            if (m == 0ull) continue;
+            // bit ll -> bit (ll + r SH) mod LPR: the ray's active chunks in order
+            const int sh = r * SH;
+            const unsigned long long mc = ((m << sh) | (m >> (LPR - sh))) & msk;
+            const int c0 = __builtin_ctzll(mc), c1 = 63 - __builtin_clzll(mc);
+            const int l0 = r * LPR + (c0 - sh + LPR) % LPR, l1 = r * LPR + (c1 - sh + LPR) % LPR;
+            const int ax = __builtin_amdgcn_readlane(fx, l0), bxv = __builtin_amdgcn_readlane(lx, l1);
+            const int ay = __builtin_amdgcn_readlane(fy, l0), byv = __builtin_amdgcn_readlane(ly, l1);
+            const int az = __builtin_amdgcn_readlane(fz, l0), bzv = __builtin_amdgcn_readlane(lz, l1);
+            ox = min(ox, min(ax, bxv)); ex = max(ex, max(ax, bxv));
+            oy = min(oy, min(ay, byv)); ey = max(ey, max(ay, byv));
+            oz = min(oz, min(az, bzv)); ez = max(ez, max(az, bzv));
+        }
         const int bx = ex - ox + 2, by = ey - oy + 2, bz = ez - oz + 2;
         // odd row and plane strides: neighbouring cells along any axis land
         // in different LDS banks
         const int rs = bx | 1;
         const int ps = (rs * by) | 1;
-        const bool fits = bx <= 64 && (long long)ps * bz <= kBoxCap;
-        const float fx = (float)st.fx, fy = (float)st.fy, fz = (float)st.fz;
-        const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
-        const float wc[8] = {zbf * gx * gy * gz, zbf * fx * gy * gz, zbf * gx * fy * gz, zbf * fx * fy * gz,
-                             zbf * gx * gy * fz, zbf * fx * gy * fz, zbf * gx * fy * fz, zbf * fx * fy * fz};
+        const bool fits = bx <= 64 && (long long)ps * bz <= CAP;
         if (!fits) {
-            if (act) {
+#pragma unroll
+            for (int q = 0; q < kScatterSpl; ++q) {
+                if (zb[q] == 0.0f) continue;
+                const float wx = (float)st[q].fx, wy = (float)st[q].fy, wz = (float)st[q].fz;
+                const float gx = 1.0f - wx, gy = 1.0f - wy, gz = 1.0f - wz;
+                const float w8[8] = {zb[q] * gx * gy * gz, zb[q] * wx * gy * gz, zb[q] * gx * wy * gz,
+                                     zb[q] * wx * wy * gz, zb[q] * gx * gy * wz, zb[q] * wx * gy * wz,
+                                     zb[q] * gx * wy * wz, zb[q] * wx * wy * wz};
                 const int off[8] = {0, 1, v.nx, v.nx + 1, sxy, sxy + 1, sxy + v.nx, sxy + v.nx + 1};
-                float *q = gZ + st.idx;
+                float *dst = gZ + st[q].idx;
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
-                    if (wc[c] != 0.0f) atomicAdd(q + off[c], wc[c]);
+                    if (w8[c] != 0.0f) atomicAdd(dst + off[c], w8[c]);
             }
             continue;
         }
-        // consecutive samples in one cell form a run (a straight ray meets
-        // each cell once); sum each run into its first lane so that every
-        // LDS atomic instruction touches distinct addresses
+        // fixed-point scale of the group: |dL/dZ| < 2^(emax - 126), at most
+        // 256 samples, weights summing to one per sample
+        int el = 0;
+#pragma unroll
+        for (int q = 0; q < kScatterSpl; ++q) el = max(el, (int)((__float_as_uint(zb[q]) >> 23) & 0xffu));
+        const int F = 180 - wave_max_exp(el);
+        // runs of a lane summed in registers, one LDS atomic per corner and run
         {
-            const int key = act ? st.idx : -1 - lane;
-            float red[8];
+            const int off[8] = {0, 1, rs, rs + 1, ps, ps + 1, ps + rs, ps + rs + 1};
+            float ra[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            int cur = -1;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) red[c] = wc[c];
-            for (int d = 1; d < 64; d <<= 1) {
-                const int kd = __shfl_down(key, d);
-                const bool same = (lane + d < 64) && (kd == key);
-                if (__ballot(same) == 0ull) break;
+            for (int q = 0; q < kScatterSpl; ++q) {
+                if (zb[q] == 0.0f) continue;
+                const int l = (st[q].iz - oz) * ps + (st[q].iy - oy) * rs + (st[q].ix - ox);
+                if (l != cur && cur >= 0) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const float o = __shfl_down(red[c], d);
-                    if (same) red[c] += o;
+                    for (int c = 0; c < 8; ++c) {
+                        if (ra[c] != 0.0f)
+                            atomicAdd(&s_box[cur + off[c]],
+                                      (unsigned long long)__double2ll_rn(ldexp((double)ra[c], F)));
+                        ra[c] = 0.0f;
+                    }
                 }
+                cur = l;
+                const float wx = (float)st[q].fx, wy = (float)st[q].fy, wz = (float)st[q].fz;
+                const float gx = 1.0f - wx, gy = 1.0f - wy, gz = 1.0f - wz;
+                ra[0] += zb[q] * gx * gy * gz;
+                ra[1] += zb[q] * wx * gy * gz;
+                ra[2] += zb[q] * gx * wy * gz;
+                ra[3] += zb[q] * wx * wy * gz;
+                ra[4] += zb[q] * gx * gy * wz;
+                ra[5] += zb[q] * wx * gy * wz;
+                ra[6] += zb[q] * gx * wy * wz;
+                ra[7] += zb[q] * wx * wy * wz;
             }
-            const int kp = __shfl_up(key, 1);
-            const bool head = act && (lane == 0 || kp != key);
-            if (head) {
-                const int l = (st.iz - oz) * ps + (st.iy - oy) * rs + (st.ix - ox);
-                const int off[8] = {0, 1, rs, rs + 1, ps, ps + 1, ps + rs, ps + rs + 1};
+            if (cur >= 0) {
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
-                    if (red[c] != 0.0f) atomicAdd(&s_box[l + off[c]], red[c]);
+                    if (ra[c] != 0.0f)
+                        atomicAdd(&s_box[cur + off[c]], (unsigned long long)__double2ll_rn(ldexp((double)ra[c], F)));
             }
         }
         __syncthreads();
-        // flush: each wave takes z-planes w, w + RB, ...; lanes cover the
-        // (row, x) pairs of a plane, consecutive lanes on consecutive x
+        // flush: lanes cover (row, x) pairs, consecutive lanes on consecutive
+        // x; four rows' LDS reads are issued before their atomics
         int lg2 = 0;
         while ((1 << lg2) < bx) ++lg2;
         const int rows_per = 64 >> lg2;
-        const int lx = lane & ((1 << lg2) - 1), sub = lane >> lg2;
-        for (int lz = w; lz < bz; lz += RB) {
-            for (int ly = sub; ly < by; ly += rows_per) {
-                if (lx >= bx) continue;
-                const int t = lz * ps + ly * rs + lx;
-                const float val = s_box[t];
-                if (val != 0.0f) {
-                    s_box[t] = 0.0f;
-                    atomicAdd(gZ + ((oz + lz) * v.ny + (oy + ly)) * v.nx + (ox + lx), val);
+        const int xl = lane & ((1 << lg2) - 1), sub = lane >> lg2;
+        const int nrows = by * bz;
+        if (xl < bx) {
+            for (int r0 = sub; r0 < nrows; r0 += 4 * rows_per) {
+                unsigned long long val[4];
+                int at[4], gi[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int row = r0 + u * rows_per;
+                    val[u] = 0ull;
+                    at[u] = gi[u] = 0;
+                    if (row < nrows) {
+                        const int zz = row / by, yy = row - zz * by;
+                        at[u] = zz * ps + yy * rs + xl;
+                        gi[u] = ((oz + zz) * v.ny + (oy + yy)) * v.nx + (ox + xl);
+                        val[u] = s_box[at[u]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (val[u] != 0ull) {
+                        s_box[at[u]] = 0ull;
+                        const float x = (float)ldexp((double)(long long)val[u], -F);
+                        if (x != 0.0f) atomicAdd(gZ + gi[u], x);
+                    }
                 }
             }
         }
@@ -1485,15 +1578,17 @@ inline int grid_for(long long n, int block)
     case CH:                                                                                   \
         if (p.speckle)                                                                         \
             hipLaunchKernelGGL((k_forward<CH, true>), dim3(grid), dim3(64), 0, st, v, p, t,    \
-                               poses, out, min_pivot, pivot_base, carry, carry_exp, xcd_group); \
+                               poses, out, min_pivot, pivot_base, carry, carry_exp, gain,      \
+                               xcd_group);                                                     \
         else                                                                                   \
             hipLaunchKernelGGL((k_forward<CH, false>), dim3(grid), dim3(64), 0, st, v, p, t,   \
-                               poses, out, min_pivot, pivot_base, carry, carry_exp, xcd_group); \
+                               poses, out, min_pivot, pivot_base, carry, carry_exp, gain,      \
+                               xcd_group);                                                     \
         break;
 
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out, float *min_pivot,
-                          int pivot_base, double *carry, int32_t *carry_exp, hipStream_t st)
+                          int pivot_base, double *carry, int32_t *carry_exp, float *gain, hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
@@ -1509,15 +1604,15 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 #define DUS_BWD_LAUNCH(CH, SPK, FUSED)                                                          \
     hipLaunchKernelGGL((k_backward<CH, SPK, FUSED>), dim3(grid), dim3(64), 0, st, v, p, t,      \
-                       poses, gsrc, target, zbar, pose_acc, loss, carry, carry_exp, xcd_group)
+                       poses, gsrc, target, zbar, pose_acc, loss, carry, carry_exp, gain, xcd_group)
 
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
         if (fused) {                                                                           \
-            if (p.speckle) DUS_BWD_LAUNCH(CH, true, true);                                     \
+            if (spk) DUS_BWD_LAUNCH(CH, true, true);                                           \
             else DUS_BWD_LAUNCH(CH, false, true);                                              \
         } else {                                                                               \
-            if (p.speckle) DUS_BWD_LAUNCH(CH, true, false);                                    \
+            if (spk) DUS_BWD_LAUNCH(CH, true, false);                                          \
             else DUS_BWD_LAUNCH(CH, false, false);                                             \
         }                                                                                      \
         break;
@@ -1526,11 +1621,12 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
                            double *pose_acc, double *loss, const double *carry,
-                           const int32_t *carry_exp, hipStream_t st)
+                           const int32_t *carry_exp, const float *gain, hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
     const bool fused = (target != nullptr);
+    const bool spk = p.speckle && !gain;      // recorded gains replace the speckle variates
     switch (chunk) {
         DUS_BWD_CASE(4)
         DUS_BWD_CASE(8)
@@ -1543,13 +1639,13 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
     for (int f = 0; f < t.n; ++f) blocks += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
     switch (scatter_rays) {
     case 2:
-        hipLaunchKernelGGL((k_scatter<2>), dim3(blocks), dim3(128), 0, st, v, t, poses, zbar, gZ, xcd_group);
+        hipLaunchKernelGGL((k_scatter<2>), dim3(blocks), dim3(64), 0, st, v, t, poses, zbar, gZ, xcd_group);
         break;
     case 4:
-        hipLaunchKernelGGL((k_scatter<4>), dim3(blocks), dim3(256), 0, st, v, t, poses, zbar, gZ, xcd_group);
+        hipLaunchKernelGGL((k_scatter<4>), dim3(blocks), dim3(64), 0, st, v, t, poses, zbar, gZ, xcd_group);
         break;
     case 8:
-        hipLaunchKernelGGL((k_scatter<8>), dim3(blocks), dim3(512), 0, st, v, t, poses, zbar, gZ, xcd_group);
+        hipLaunchKernelGGL((k_scatter<8>), dim3(blocks), dim3(64), 0, st, v, t, poses, zbar, gZ, xcd_group);
         break;
     default:
         return hipErrorInvalidValue;
