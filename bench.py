@@ -127,8 +127,7 @@ def main():
     import torch
 
     from paper_2508_06768_amd import synth
-    from paper_2508_06768_amd.render import (FusedStep, Geometry, footprint_voxels, render,
-                                             render_backward)
+    from paper_2508_06768_amd.render import FusedStep, Geometry, footprint_voxels, render
 
     dev = torch.device("cuda:0")
     B = args.poses
@@ -203,28 +202,25 @@ def main():
         plain_ms = timed(plain, max(2, args.steps // 4), ev)
         log(f"bench: plain per-pose step {plain_ms:.3f} ms")
 
-    # dominant kernels alone (same kernels as inside the step): blur off so a
-    # call launches exactly one kernel
-    import copy
-    ph1 = copy.copy(case.phys)
-    ph1.blur_on = False
-    g_nb = Geometry(case.Z.shape, case.spacing, case.origin, case.fans, ph1)
-    from paper_2508_06768_amd.render import set_schedule
-    set_schedule(**step.get_schedule())
-    ws_b = g_nb.workspace(True, dev)
-    ms_k_fwd = timed(lambda: render(Z, poses, g_nb, out=out), 10, ev)
-    gsrc = torch.randn(N, device=dev) * 1e-6
-    ms_k_bwd = timed(lambda: render_backward(Z, poses, g_nb, gsrc, want_Z=True, want_pose=False, grad_Z=gZ,
-                                             ws=ws_b), 10, ev)
+    # per-kernel durations inside the step: the same plan launched eagerly
+    # with HIP events at the phase boundaries (on the launch stream)
+    reps = max(5, args.steps // 2)
+    phases = None
+    for _ in range(reps):
+        ph_ms = step.step_timed(Z, poses, target, loss=loss, grad_Z=gZ, grad_pose=gp)
+        phases = ph_ms if phases is None else {k: phases[k] + v for k, v in ph_ms.items()}
+    phases = {k: v / reps for k, v in phases.items()}
+    log(f"bench: phases (ms) {json.dumps(phases)}")
     vfp = footprint_voxels(poses, geom)
     n_vox = int(np.prod(case.Z.shape))
-    bytes_fwd = 4.0 * N + 4.0 * vfp
-    bytes_bwd = 4.0 * N + 4.0 * vfp + 8.0 * vfp
-    kern = {
-        "forward": {"ms": ms_k_fwd, "alg_bytes": bytes_fwd, "GBs": bytes_fwd / (ms_k_fwd * 1e-3) / 1e9},
-        "adjoint": {"ms": ms_k_bwd, "alg_bytes": bytes_bwd, "GBs": bytes_bwd / (ms_k_bwd * 1e-3) / 1e9},
-    }
-    dom = "adjoint" if ms_k_bwd >= ms_k_fwd else "forward"
+    # algorithmic bytes per launch (per ray-sample figures times N, per
+    # footprint voxel figures times V_fp): forward 4 N (pixels) + 4 V_fp
+    # (volume); adjoint scan 4 N (dL/dI) + 4 V_fp (volume); scatter
+    # 8 V_fp (gradient read-modify-write)
+    alg = {"forward": 4.0 * N + 4.0 * vfp, "adjoint": 4.0 * N + 4.0 * vfp, "scatter": 8.0 * vfp}
+    kern = {k: {"ms": phases[k], "alg_bytes": alg[k], "GBs": alg[k] / (phases[k] * 1e-3) / 1e9}
+            for k in ("forward", "adjoint", "scatter")}
+    dom = max(kern, key=lambda k: kern[k]["ms"])
     log(f"bench: kernels {json.dumps(kern)} footprint voxels {vfp}")
 
     if args.calib_copy:
@@ -263,6 +259,7 @@ def main():
         "plain_per_pose": None if plain_ms is None else {"ms": plain_ms, "value": N / (plain_ms * 1e-3)},
         "plain_forward_per_pose": (None if plain_fwd_ms is None
                                    else {"ms": plain_fwd_ms, "value": N / (plain_fwd_ms * 1e-3)}),
+        "phases_ms": phases,
         "kernels": kern,
         "roofline": {
             "bound": "hbm",
@@ -272,6 +269,8 @@ def main():
             "unit": "GB/s",
             "frac": kern[dom]["GBs"] / HBM_PEAK_GBS,
             "traffic": measured_traffic() if dom == "adjoint" else None,
+            "alg_bytes": kern[dom]["alg_bytes"],
+            "ms": kern[dom]["ms"],
         },
         "schedule": step.get_schedule(),
         "autotune_trials": None if tune is None else tune.get("trials"),

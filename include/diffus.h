@@ -213,6 +213,38 @@ int dus_plan_get_schedule(const dus_plan *plan, dus_schedule *sched);
 int dus_plan_step(dus_plan *plan, const float *Z, const float *poses, const float *target,
                   float *bmode, double *loss, float *grad_Z, float *grad_pose,
                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Phases of a plan step, in launch order (measurement and tracing):
+ *   CLEAR      fill kernels for the pose accumulators and grad_Z
+ *   FORWARD    forward kernel (pixels, tile carries, per-pixel gains)
+ *   BLUR_LOSS  blur, MSE residual and loss partials, blur transpose (blur on)
+ *   ADJOINT    adjoint scan kernel (dL/dZ per sample, pose sums; with blur
+ *              off it also forms the loss partials)
+ *   SCATTER    trilinear scatter of dL/dZ into grad_Z
+ *   FINISH     loss reduction and pose-gradient kernel
+ */
+enum {
+    DUS_PHASE_CLEAR = 0,
+    DUS_PHASE_FORWARD = 1,
+    DUS_PHASE_BLUR_LOSS = 2,
+    DUS_PHASE_ADJOINT = 3,
+    DUS_PHASE_SCATTER = 4,
+    DUS_PHASE_FINISH = 5,
+    DUS_NUM_PHASES = 6
+};
+
+/*
+ * dus_plan_step without graph replay, with a HIP event recorded on `stream`
+ * at every phase boundary.  Same arguments and results as dus_plan_step;
+ * ms[DUS_PHASE_*] receives each phase's duration in milliseconds (0 for a
+ * phase the step does not run).  Blocks the calling thread until the step
+ * has finished on the device.  Creates and destroys its events (no device
+ * memory is allocated).
+ */
+int dus_plan_step_timed(dus_plan *plan, const float *Z, const float *poses, const float *target,
+                        float *bmode, double *loss, float *grad_Z, float *grad_pose,
+                        void *ws, size_t ws_bytes, void *stream, float *ms);
 void dus_plan_destroy(dus_plan *plan);
 
 #ifdef __cplusplus

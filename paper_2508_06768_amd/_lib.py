@@ -19,6 +19,8 @@ DUS_OK, DUS_EINVAL, DUS_ESHAPE, DUS_EWORKSPACE, DUS_EHIP, DUS_EUNSUPPORTED = 0, 
 REFL_ABS, REFL_SIGNED = 0, 1
 ATTEN_IN_SYSTEM, ATTEN_POST_HOC, ATTEN_OFF = 0, 1, 2
 PLAN_POSE_ONLY, PLAN_ZERO_GRAD_Z, PLAN_NO_GRAPH = 1, 2, 4
+# phases of a plan step (DUS_PHASE_*), in launch order
+PHASES = ("clear", "forward", "blur_loss", "adjoint", "scatter", "finish")
 MAX_SAMPLES, MAX_RAYS, MAX_BLUR_RADIUS = 16384, 65536, 32
 
 
@@ -68,6 +70,8 @@ SIGNATURES = {
     "dus_plan_set_schedule": (ctypes.c_int, [c_vp, ctypes.POINTER(DusSchedule)]),
     "dus_plan_get_schedule": (ctypes.c_int, [c_vp, ctypes.POINTER(DusSchedule)]),
     "dus_plan_step": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "dus_plan_step_timed": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp,
+                                           ctypes.POINTER(ctypes.c_float)]),
     "dus_plan_destroy": (None, [c_vp]),
 }
 

@@ -570,56 +570,71 @@ int dus_plan_get_schedule(const dus_plan *p, dus_schedule *sc)
     return DUS_OK;
 }
 
+// ev (optional): DUS_NUM_PHASES + 1 events recorded at the phase boundaries
 static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const float *target, float *bmode,
-                        double *loss, float *grad_Z, float *grad_pose, void *ws, hipStream_t st)
+                        double *loss, float *grad_Z, float *grad_pose, void *ws, hipStream_t st,
+                        hipEvent_t *ev = nullptr)
 {
+    auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
     const dus::VolArgs va = vol_args(Z, &p->vol);
     const dus::PhysArgs pa = phys_args(&p->phys);
     const int n_poses = (int)p->fans.size();
     double *acc = reinterpret_cast<double *>((char *)ws + p->ws.acc);
     float *zbar = reinterpret_cast<float *>((char *)ws + p->ws.zb);
     float *gZ = (p->flags & DUS_PLAN_POSE_ONLY) ? nullptr : grad_Z;
-    if (grad_pose) DUS_HIP(dus::launch_zero_f64(acc, (int64_t)n_poses * dus::kPoseAcc, st), "zero kernel");
     double *part = reinterpret_cast<double *>((char *)ws + p->ws.part);
     int64_t n_part = 0;
-    if (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z))
-        DUS_HIP(dus::launch_zero_f32(gZ, (int64_t)p->vol.nx * p->vol.ny * p->vol.nz, st), "zero kernel");
     const Sched &sc = p->sched;
-    // the forward records its tile carries; the adjoint starts from them
+    // the forward records its tile carries and per-pixel gains; the adjoint
+    // starts from them
     double *car = reinterpret_cast<double *>((char *)ws + p->ws.car);
     int32_t *cex = reinterpret_cast<int32_t *>((char *)ws + p->ws.cex);
     float *gain = p->ws.gain_bytes ? reinterpret_cast<float *>((char *)ws + p->ws.gain) : nullptr;
-    if (p->phys.blur_on) {
-        float *pre = reinterpret_cast<float *>((char *)ws + p->ws.pre);
-        float *res = reinterpret_cast<float *>((char *)ws + p->ws.res);
-        float *eb = reinterpret_cast<float *>((char *)ws + p->ws.eb);
+    const bool blur = p->phys.blur_on != 0;
+    const bool fwd = blur || bmode;               // the forward kernel runs
+    DUS_HIP(mark(DUS_PHASE_CLEAR), "event");
+    if (grad_pose) DUS_HIP(dus::launch_zero_f64(acc, (int64_t)n_poses * dus::kPoseAcc, st), "zero kernel");
+    if (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z))
+        DUS_HIP(dus::launch_zero_f32(gZ, (int64_t)p->vol.nx * p->vol.ny * p->vol.nz, st), "zero kernel");
+    DUS_HIP(mark(DUS_PHASE_FORWARD), "event");
+    if (fwd) {
         int s;
-        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, pre, nullptr, st, car, cex, gain)) != DUS_OK) return s;
+        float *img = blur ? reinterpret_cast<float *>((char *)ws + p->ws.pre) : bmode;
+        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, img, nullptr, st, car, cex, gain)) != DUS_OK) return s;
+    }
+    DUS_HIP(mark(DUS_PHASE_BLUR_LOSS), "event");
+    const float *eb = nullptr;
+    if (blur) {
+        const float *pre = reinterpret_cast<float *>((char *)ws + p->ws.pre);
+        float *res = reinterpret_cast<float *>((char *)ws + p->ws.res);
+        float *ebw = reinterpret_cast<float *>((char *)ws + p->ws.eb);
         for (const auto &t : p->tabs) {
-            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, eb, loss ? part + n_part : nullptr, st),
+            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, ebw, loss ? part + n_part : nullptr, st),
                     "blur/loss kernel");
             n_part += t.total_blur_blocks;
         }
-        if (gZ || grad_pose)
-            for (const auto &t : p->tabs)
-                DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, eb, nullptr, zbar, gZ,
-                                             grad_pose ? acc : nullptr, nullptr, car, cex, gain, st),
-                        "adjoint kernel");
-    } else {
-        if (bmode) {
-            int s;
-            if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, bmode, nullptr, st, car, cex, gain)) != DUS_OK) return s;
-        }
-        for (const auto &t : p->tabs) {
-            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, nullptr, target, zbar, gZ,
-                                         grad_pose ? acc : nullptr, loss ? part + n_part : nullptr,
-                                         bmode ? car : nullptr, bmode ? cex : nullptr, bmode ? gain : nullptr, st),
-                    "fused adjoint kernel");
-            n_part += t.total_rays;
-        }
+        eb = ebw;
     }
+    DUS_HIP(mark(DUS_PHASE_ADJOINT), "event");
+    // with blur the adjoint starts from B^T of the residual; without it, the
+    // adjoint forms the residual and the loss partials itself
+    const bool adj = blur ? (gZ || grad_pose) : true;
+    if (adj)
+        for (const auto &t : p->tabs) {
+            DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, blur ? nullptr : target, zbar,
+                                        grad_pose ? acc : nullptr, (!blur && loss) ? part + n_part : nullptr,
+                                        fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? gain : nullptr, st),
+                    "adjoint kernel");
+            if (!blur) n_part += t.total_rays;
+        }
+    DUS_HIP(mark(DUS_PHASE_SCATTER), "event");
+    if (adj && gZ)
+        for (const auto &t : p->tabs)
+            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, poses, zbar, gZ, st), "scatter kernel");
+    DUS_HIP(mark(DUS_PHASE_FINISH), "event");
     if (loss) DUS_HIP(dus::launch_sum_f64(part, n_part, loss, st), "loss sum kernel");
     if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel");
+    DUS_HIP(mark(DUS_NUM_PHASES), "event");
     return DUS_OK;
 }
 
@@ -658,6 +673,34 @@ int dus_plan_step(dus_plan *p, const float *Z, const float *poses, const float *
         p->key_ws_bytes = ws_bytes;
     }
     DUS_HIP(hipGraphLaunch(p->exec, st), "graph launch");
+    return DUS_OK;
+}
+
+int dus_plan_step_timed(dus_plan *p, const float *Z, const float *poses, const float *target, float *bmode,
+                        double *loss, float *grad_Z, float *grad_pose, void *ws, size_t ws_bytes, void *stream,
+                        float *ms)
+{
+    if (!p) return fail(DUS_EINVAL, "plan is NULL");
+    if (!ms) return fail(DUS_EINVAL, "ms is NULL");
+    int s;
+    if ((s = check_ws(ws, ws_bytes, p->ws.total)) != DUS_OK) return s;
+    if (p->extent > 0 && (!Z || !poses || !target)) return fail(DUS_EINVAL, "Z, poses and target are required");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t ev[DUS_NUM_PHASES + 1] = {};
+    int made = 0;
+    hipError_t e = hipSuccess;
+    for (; made <= DUS_NUM_PHASES; ++made)
+        if ((e = hipEventCreate(&ev[made])) != hipSuccess) break;
+    if (e == hipSuccess) {
+        s = plan_enqueue(p, Z, poses, target, bmode, loss, grad_Z, grad_pose, ws, st, ev);
+        if (s == DUS_OK) {
+            e = hipEventSynchronize(ev[DUS_NUM_PHASES]);
+            for (int i = 0; i < DUS_NUM_PHASES && e == hipSuccess; ++i) e = hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]);
+        }
+    }
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    if (s != DUS_OK) return s;
+    if (e != hipSuccess) return hip_fail(e, "phase events");
     return DUS_OK;
 }
 

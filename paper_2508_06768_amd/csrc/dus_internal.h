@@ -78,6 +78,15 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
                            const float *gsrc, const float *target, float *zbar, float *gZ,
                            double *pose_acc, double *loss, const double *carry,
                            const int32_t *carry_exp, const float *gain, hipStream_t st);
+// the two halves of launch_backward: the adjoint scan (dL/dZ per sample into
+// zbar, pose sums, fused loss partials) and the scatter of zbar into gZ
+hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
+                          const FanTable &t, const float *poses, const float *gsrc,
+                          const float *target, float *zbar, double *pose_acc, double *loss,
+                          const double *carry, const int32_t *carry_exp, const float *gain,
+                          hipStream_t st);
+hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
+                          const float *poses, const float *zbar, float *gZ, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st);
 // image = B pre (optional), ebar = B^T (2 (image - target) / P); loss

@@ -1617,11 +1617,11 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
         }                                                                                      \
         break;
 
-hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
-                           const PhysArgs &p, const FanTable &t, const float *poses,
-                           const float *gsrc, const float *target, float *zbar, float *gZ,
-                           double *pose_acc, double *loss, const double *carry,
-                           const int32_t *carry_exp, const float *gain, hipStream_t st)
+hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
+                          const FanTable &t, const float *poses, const float *gsrc,
+                          const float *target, float *zbar, double *pose_acc, double *loss,
+                          const double *carry, const int32_t *carry_exp, const float *gain,
+                          hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
@@ -1633,8 +1633,13 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
     default:
         return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !gZ) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
+                          const float *poses, const float *zbar, float *gZ, hipStream_t st)
+{
+    if (t.total_rays <= 0 || !gZ) return hipSuccess;
     int blocks = 0;
     for (int f = 0; f < t.n; ++f) blocks += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
     switch (scatter_rays) {
@@ -1651,6 +1656,18 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
+                           const PhysArgs &p, const FanTable &t, const float *poses,
+                           const float *gsrc, const float *target, float *zbar, float *gZ,
+                           double *pose_acc, double *loss, const double *carry,
+                           const int32_t *carry_exp, const float *gain, hipStream_t st)
+{
+    hipError_t e = launch_adjoint(chunk, xcd_group, v, p, t, poses, gsrc, target, zbar, pose_acc, loss, carry,
+                                  carry_exp, gain, st);
+    if (e != hipSuccess) return e;
+    return launch_scatter(scatter_rays, xcd_group, v, t, poses, zbar, gZ, st);
 }
 
 #define DUS_BLUR_LAUNCH(MODE, TGT, IMG, LOSS)                                                       \

@@ -261,6 +261,17 @@ class FusedStep:
                                        _ptr(grad_Z), _ptr(grad_pose), _ptr(ws), ws.numel(), _stream()),
               "dus_plan_step")
 
+    def step_timed(self, Z, poses, target, bmode=None, loss=None, grad_Z=None, grad_pose=None) -> dict:
+        """One step launched eagerly with HIP events at the phase boundaries;
+        returns {phase: ms} (blocks until the step has finished)."""
+        _check_inputs(Z, poses, self.geom)
+        ws = self.workspace(Z.device)
+        ms = (ctypes.c_float * len(_lib.PHASES))()
+        check(_lib.lib().dus_plan_step_timed(self._h, _ptr(Z), _ptr(poses), _ptr(target), _ptr(bmode), _ptr(loss),
+                                             _ptr(grad_Z), _ptr(grad_pose), _ptr(ws), ws.numel(), _stream(), ms),
+              "dus_plan_step_timed")
+        return {name: float(ms[i]) for i, name in enumerate(_lib.PHASES)}
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.lib().dus_plan_destroy(self._h)

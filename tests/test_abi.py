@@ -161,6 +161,9 @@ def test_plan_validation():
         == _lib.DUS_EINVAL
     assert h.value is None
     assert L.dus_plan_step(None, None, None, None, None, None, None, None, None, 0, None) == _lib.DUS_EINVAL
+    ms = (ctypes.c_float * len(_lib.PHASES))()
+    assert L.dus_plan_step_timed(None, None, None, None, None, None, None, None, None, 0, None, ms) \
+        == _lib.DUS_EINVAL
     assert L.dus_plan_workspace_bytes(None) == _lib.DUS_EINVAL
     L.dus_plan_destroy(None)
 

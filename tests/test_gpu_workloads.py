@@ -129,8 +129,8 @@ def test_schedules_agree():
     base = get_schedule()
     outs = []
     try:
-        for fc, bc, xg in [(4, 4, 1), (8, 8, 16), (16, 4, 64), (8, 4, 3)]:
-            set_schedule(fwd_chunk=fc, bwd_chunk=bc, xcd_group=xg)
+        for fc, bc, xg, sr in [(4, 4, 1, 2), (8, 8, 16, 4), (16, 4, 64, 8), (8, 4, 3, 8)]:
+            set_schedule(fwd_chunk=fc, bwd_chunk=bc, xcd_group=xg, scatter_rays=sr)
             img = render(Z, P, geom).cpu().numpy().astype(np.float64)
             gZ, gp = render_backward(Z, P, geom, w)
             outs.append((img, gZ.cpu().numpy().astype(np.float64), gp.cpu().numpy().astype(np.float64)))
@@ -163,6 +163,10 @@ def test_graph_replays_agree():
     eager.step(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
     torch.cuda.synchronize()
     ref = (bm.cpu().numpy(), loss.item(), gZ.cpu().numpy(), gp.cpu().numpy())
+    # the phase-timed step launches the same kernels eagerly
+    ms = eager.step_timed(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+    res.append((bm.cpu().numpy().copy(), loss.item(), gZ.cpu().numpy().copy(), gp.cpu().numpy().copy()))
+    assert all(v >= 0.0 for v in ms.values()) and ms["forward"] > 0 and ms["adjoint"] > 0 and ms["scatter"] > 0
     for r in res:
         np.testing.assert_array_equal(r[0], ref[0])
         assert r[1] == pytest.approx(ref[1], rel=1e-12)
