@@ -190,7 +190,9 @@ typedef struct {
     int32_t fwd_chunk;        /* interfaces per lane per tile, forward: 4, 8 or 16 */
     int32_t bwd_chunk;        /* same for the adjoint: 4 or 8 */
     int32_t xcd_group;        /* consecutive rays kept on one XCD: 1..64 */
-    int32_t scatter_rays;     /* neighbouring rays sharing one LDS box in the dL/dZ scatter: 2, 4 or 8 */
+    int32_t scatter_rays;     /* neighbouring rays per wavefront (one LDS box) in the dL/dZ scatter:
+                                 2, 4 or 8; 0 (the default) picks 8, or 2 for launches of fewer
+                                 than 16384 rays */
 } dus_schedule;
 
 /* Process-wide schedule used by dus_render_bmode / dus_render_bmode_backward

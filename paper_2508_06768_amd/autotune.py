@@ -20,7 +20,7 @@ import torch
 
 FWD_CHUNKS = (4, 8, 16)
 BWD_CHUNKS = (4, 8)
-XCD_GROUPS = (1, 4, 16, 64)
+XCD_GROUPS = (1, 4, 8, 16, 32, 64)
 SCATTER_RAYS = (2, 4, 8)
 
 

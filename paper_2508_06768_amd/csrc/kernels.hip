@@ -1640,6 +1640,10 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
                           const float *poses, const float *zbar, float *gZ, hipStream_t st)
 {
     if (t.total_rays <= 0 || !gZ) return hipSuccess;
+    // 0: automatic.  Eight rays per wavefront, unless that leaves fewer than
+    // two wavefronts per SIMD; then two (more wavefronts, each walking a
+    // quarter as many groups)
+    if (scatter_rays == 0) scatter_rays = (t.total_rays / 8 < 2048) ? 2 : 8;
     int blocks = 0;
     for (int f = 0; f < t.n; ++f) blocks += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
     switch (scatter_rays) {

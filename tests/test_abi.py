@@ -174,3 +174,23 @@ def test_status_strings():
         assert L.dus_status_string(s)
     assert L.dus_version() >= 1
     assert np.int32(_lib.DUS_OK) == 0
+
+
+def test_schedule_validation():
+    """Schedules are validated on the host; 0 fields select the defaults
+    (scatter_rays 0 = automatic)."""
+    L = _lib.lib()
+    old = _lib.DusSchedule()
+    assert L.dus_get_schedule(ctypes.byref(old)) == _lib.DUS_OK
+    try:
+        for bad in [(3, 0, 0, 0), (0, 16, 0, 0), (0, 0, 65, 0), (0, 0, 0, 3), (0, 0, 0, 16)]:
+            assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(*bad))) == _lib.DUS_EINVAL, bad
+        assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(0, 0, 0, 0))) == _lib.DUS_OK
+        got = _lib.DusSchedule()
+        assert L.dus_get_schedule(ctypes.byref(got)) == _lib.DUS_OK
+        assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays) == (8, 4, 16, 0)
+        assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(16, 8, 64, 2))) == _lib.DUS_OK
+        assert L.dus_get_schedule(ctypes.byref(got)) == _lib.DUS_OK
+        assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays) == (16, 8, 64, 2)
+    finally:
+        L.dus_set_schedule(ctypes.byref(old))
