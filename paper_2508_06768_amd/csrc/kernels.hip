@@ -286,8 +286,10 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        // one 32 x 32 -> 64-bit product per multiplier (low and high words)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -301,10 +303,13 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
     out[3] = c3;
 }
 
+// unit-mean Rayleigh: sqrt(-2 ln u) sqrt(2/pi) = sqrt(-(4 ln 2 / pi) log2 u);
+// u in [2^-24, 1] is a normal number, so the hardware log2 and square root
+// (about 1 ulp) apply directly
 __device__ __forceinline__ float rayleigh(uint32_t x)
 {
     const float u = (float)((x >> 8) + 1u) * 0x1p-24f;
-    return sqrtf(-2.0f * logf(u)) * 0.7978845608028654f;   // sqrt(2/pi)
+    return __builtin_amdgcn_sqrtf(-0.88254240061060638f * __builtin_amdgcn_logf(u));
 }
 
 // Speckle inputs of one tile [t0, t0+T): granular variates per pixel and the
@@ -332,23 +337,40 @@ __device__ __forceinline__ void speckle_fill(const PhysArgs &p, int t0, int j, i
     }
 }
 
-// Gain of pixel k (tile index i): post-hoc attenuation times speckle
+// per-launch constants of pixel_gain: 1/(S-1) and 1/cell
+struct GainK {
+    float inv_sm1, inv_cell;
+};
+
+__device__ __forceinline__ GainK gain_consts(const PhysArgs &p, int S)
+{
+    return GainK{S > 1 ? 1.0f / (float)(S - 1) : 0.0f, 1.0f / (float)p.cell};
+}
+
+// Gain of pixel k (tile index i): post-hoc attenuation times speckle.
+// zeta = k/(S-1) and the cell fraction come from reciprocals (within an ulp
+// of the quotients); the cell index is exact.
 template <bool SPK>
-__device__ __forceinline__ float pixel_gain(const PhysArgs &p, int k, int i, int S, int t0,
+__device__ __forceinline__ float pixel_gain(const PhysArgs &p, const GainK &gk, int k, int i, int t0,
                                             float postc, const float *s_xig, const float *s_xir)
 {
     float g = 1.0f;
     if (p.atten == 1) g = exp2f((float)((double)k * (double)postc));
     if (SPK) {
-        const float zeta = S > 1 ? (float)k / (float)(S - 1) : 0.0f;
+        const float zeta = (float)k * gk.inv_sm1;
         const int cell = p.cell;
-        const int c = k / cell;
-        const float fr = (float)(k - c * cell) / (float)cell;
+        int c = (int)((float)k * gk.inv_cell);
+        int r = k - c * cell;
+        if (r < 0) { --c; r += cell; }
+        if (r >= cell) { ++c; r -= cell; }
+        const float fr = (float)r * gk.inv_cell;
         const int c_lo = t0 / cell;
         const float xr = (1.0f - fr) * s_xir[c - c_lo] + fr * s_xir[c + 1 - c_lo];
         const float xg = s_xig[i];
+        // zeta^gam with zeta in [1/(S-1), 1] (a normal number); a power below
+        // 2^-126 may flush to zero, which leaves the FP32 gain unchanged
         float pw;
-        if (zeta > 0.0f) pw = exp2f(p.gam * log2f(zeta));
+        if (zeta > 0.0f) pw = __builtin_amdgcn_exp2f(p.gam * __builtin_amdgcn_logf(zeta));
         else pw = (p.gam == 0.0f) ? 1.0f : 0.0f;
         g *= 1.0f + p.Ar * pw * (xr - 1.0f) + (p.Ag0 + p.Ag1 * zeta) * (xg - 1.0f);
     }
@@ -523,6 +545,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     const double sgn = absm ? 1.0 : -1.0;
     const double a2 = ray.a2;
     const float postc = posthoc_coef(p, fr.ds);
+    const GainK gk = gain_consts(p, fr.n_samples);
     const long long obase = fr.out_offset + (long long)j * S;
 
     double c0 = 0.0, c1 = 1.0, cD = 1.0, zprev = 0.0;
@@ -606,7 +629,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             if (k < S) {
                 float pix = s_pix[pad4(i)];
                 if (SPK || p.atten == 1) {
-                    const float gn = pixel_gain<SPK>(p, k, i, S, t0, postc, s_xig, s_xir);
+                    const float gn = pixel_gain<SPK>(p, gk, k, i, t0, postc, s_xig, s_xir);
                     pix *= gn;
                     if (gain_out) gain_out[obase + k] = gn;
                 }
@@ -693,6 +716,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     const double sgn = absm ? 1.0 : -1.0;
     const double a2 = ray.a2;
     const float postc = posthoc_coef(p, fr.ds);
+    const GainK gk = gain_consts(p, fr.n_samples);
     const long long obase = fr.out_offset + (long long)j * S;
     const int ntiles = (S + T - 1) / T;
     const double inv_npix = 1.0 / ((double)fr.n_rays * (double)S);
@@ -799,7 +823,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             for (int m = 0; m < C; ++m) {
                 const int i = m * 64 + lane;
                 const int k = t0 + i;
-                const float gain = (has_gain && k < S) ? pixel_gain<SPK>(p, k, i, S, t0, postc, s_xig, s_xir) : 1.0f;
+                const float gain = (has_gain && k < S) ? pixel_gain<SPK>(p, gk, k, i, t0, postc, s_xig, s_xir) : 1.0f;
                 if (FUSED) s_gain[pad4(i)] = gain;
                 else s_eb[pad4(i)] *= gain;
             }
@@ -1554,10 +1578,11 @@ __global__ __launch_bounds__(64) void k_gain(PhysArgs p, FanRec fr, float *__res
     if (SPK) speckle_fill<T>(p, t0, j, fr.speckle_id, lane, s_xig, s_xir);
     __syncthreads();
     const float postc = posthoc_coef(p, fr.ds);
+    const GainK gk = gain_consts(p, fr.n_samples);
     for (int m = 0; m < T / 64; ++m) {
         const int i = m * 64 + lane;
         const int k = t0 + i;
-        if (k < S) out[(long long)j * S + k] = pixel_gain<SPK>(p, k, i, S, t0, postc, s_xig, s_xir);
+        if (k < S) out[(long long)j * S + k] = pixel_gain<SPK>(p, gk, k, i, t0, postc, s_xig, s_xir);
     }
 }
 
