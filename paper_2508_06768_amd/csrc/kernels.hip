@@ -31,6 +31,7 @@
 // reverse recurrence as an associative affine suffix scan over lanes, and
 // scatters dL/dZ into the volume gradient with FP32 atomics; pose gradients
 // are reduced per ray in FP64.
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -74,15 +75,13 @@ __device__ __forceinline__ double wave_min(double x)
     return x;
 }
 
-// FP64 reciprocal: hardware estimate refined by two Newton steps.
+// FP64 reciprocal: hardware estimate refined by one Newton step (the step
+// squares the estimate's relative error: below 2^-44 even for a
+// single-precision estimate)
 __device__ __forceinline__ double rcp64(double b)
 {
-    double r = __builtin_amdgcn_rcp(b);
-    double e = fma(-b, r, 1.0);
-    r = fma(e, r, r);
-    e = fma(-b, r, 1.0);
-    r = fma(e, r, r);
-    return r;
+    const double r = __builtin_amdgcn_rcp(b);
+    return fma(fma(-b, r, 1.0), r, r);
 }
 
 __device__ __forceinline__ double div64(double a, double b)
@@ -267,10 +266,19 @@ __device__ __forceinline__ double trilinear(const float *__restrict__ Z, int nx,
     return lerp(b0, b1, s.fz);
 }
 
-// Eq. 1 reflection coefficient between samples zl (shallower) and zr
-__device__ __forceinline__ double iface_rho(double zl, double zr, bool absm)
+// Eq. 1 reflection coefficient between samples zl (shallower) and zr; dq
+// (optional) receives d rho/d zr = dq zl and d rho/d zl = -dq zr, i.e.
+// dq = 2 s / (zl + zr)^2 with s = sign(zr - zl) (ABS, sign(0) = 0) or 1
+__device__ __forceinline__ double iface_rho(double zl, double zr, bool absm, double *dq = nullptr)
 {
-    const double r = div64(zr - zl, zr + zl);
+    const double sum = zl + zr, dif = zr - zl;
+    const double is = rcp64(sum);
+    const double q = dif * is;
+    const double r = fma(fma(-sum, q, dif), is, q);
+    if (dq) {
+        const double sg = absm ? ((zr > zl) ? 1.0 : ((zr < zl) ? -1.0 : 0.0)) : 1.0;
+        *dq = 2.0 * sg * is * is;
+    }
     return absm ? fabs(r) : r;
 }
 
@@ -391,7 +399,8 @@ __device__ __forceinline__ float posthoc_coef(const PhysArgs &p, float ds)
 template <int C, bool KEEPZ, bool KEEPG = false>
 __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, int t0, int S,
                                             bool absm, int lane, double &zprev, double *s_rho,
-                                            double *s_z, float *s_g = nullptr, double *s_zc = nullptr)
+                                            double *s_z, float *s_g = nullptr, double *s_zc = nullptr,
+                                            double *s_dq = nullptr)
 {
     constexpr int T = 64 * C;
     const int sxy = v.nx * v.ny;
@@ -405,10 +414,13 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
         double zm = __shfl_up(z, 1);
         if (lane == 0) zm = zprev;
         zprev = lane_read(z, 63);
-        double rho = 0.0;
-        if (k >= 1 && k < S) rho = iface_rho(zm, z, absm);
+        double rho = 0.0, dq = 0.0;
+        if (k >= 1 && k < S) rho = iface_rho(zm, z, absm, KEEPZ ? &dq : nullptr);
         s_rho[pad8(i)] = rho;
-        if (KEEPZ) s_z[pad8(i)] = z;
+        if (KEEPZ) {
+            s_z[pad8(i)] = z;
+            s_dq[pad8(i)] = dq;
+        }
         if (s_zc && lane == 63 && (jj & 3) == 3) s_zc[jj >> 2] = z;
         if (KEEPG) {
             s_g[i] = (float)gu[0];
@@ -696,6 +708,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     __shared__ float s_g[3 * T];     // dZ/du of every sample of the tile
     __shared__ double s_rho[T + T / 16];
     __shared__ double s_z[T + T / 16];
+    __shared__ double s_dq[T + T / 16];   // d rho / dZ factor of every interface of the tile
     __shared__ float s_eb[T + T / 32];
     __shared__ float s_gain[FUSED ? T + T / 32 : 1];
     __shared__ float s_xig[SPK ? T : 1];
@@ -788,9 +801,9 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         const double zstart = s_carry[t][3];
         double zprev = zstart;
         if (pose_acc)
-            gather_tile<C, true, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g);
+            gather_tile<C, true, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, nullptr, s_dq);
         else
-            gather_tile<C, true, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z);
+            gather_tile<C, true, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, nullptr, nullptr, s_dq);
         if (SPK) speckle_fill<T>(p, t0, j, fr.speckle_id, lane, s_xig, s_xir);
         __syncthreads();
         // dL/de (or the target for the fused loss) staged through LDS: the C
@@ -965,16 +978,8 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                     const double dE = -2.0 * a2 * r;
                     const double rb = la.l0 * fma(v0, dA, v1 * dB) + la.l1 * v0 + eb * D * w1p * w1p + la.lD * D * dE;
                     // Eq. 1 on this interface (samples zl = Z_{k-1}, zr = Z_k):
-                    // d rho/d zr = s 2 zl / (zl + zr)^2, d rho/d zl = -s 2 zr / (zl + zr)^2,
-                    // s = sign(zr - zl) (ABS, sign(0) = 0) or 1; keep rb 2 s / (zl + zr)^2
-                    if (rb != 0.0) {
-                        const double zr = s_z[pad8(base + i)];
-                        const double zl = (base + i > 0) ? s_z[pad8(base + i - 1)] : zstart;
-                        const double zs = zl + zr;
-                        double sg = 1.0;
-                        if (absm) sg = (zr > zl) ? 1.0 : ((zr < zl) ? -1.0 : 0.0);
-                        qz = 2.0 * sg * rb * rcp64(zs * zs);
-                    }
+                    // dL/dzr = rb dq zl, dL/dzl = -rb dq zr (dq from the gather)
+                    qz = rb * s_dq[pad8(base + i)];
                     lc = la;
                     const double v0n = fma(v0, m.m00, v1 * m.m10);
                     v0 = v0n;
@@ -1061,8 +1066,8 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
 // --------------------------------------------------------------------------
 // scatter of dL/dZ_k: trilinear weights into the volume gradient.  One
 // wavefront takes RB neighbouring rays of one fan (64/RB lanes per ray) and
-// walks them together in groups of 256/RB depths; every lane owns 4
-// consecutive depths of its ray.  A straight ray meets each cell once, so a
+// one segment of `seg` depths (blockIdx.y), and walks them together in
+// groups of 256/RB depths; every lane owns 4 consecutive depths of its ray.  A straight ray meets each cell once, so a
 // lane's consecutive samples in one cell form a run that it sums in
 // registers before touching memory.  The stencils of a group fill a small
 // box of the volume (neighbouring rays of a fan overlap); the runs go into an
@@ -1099,7 +1104,7 @@ __device__ __forceinline__ int wave_max_exp(int e)
 template <int RB>
 __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const float *__restrict__ poses,
                                                 const float *__restrict__ zbar, float *__restrict__ gZ,
-                                                int xgrp)
+                                                int seg, int xgrp)
 {
     constexpr int LPR = 64 / RB;                 // lanes per ray
     constexpr int G = LPR * kScatterSpl;         // depths per group
@@ -1126,6 +1131,9 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
     const int j = (b - acc) * RB + slot;
     const bool ray_ok = j < fr.n_rays;
     const int S = fr.n_samples;
+    const int k_begin = blockIdx.y * seg;
+    if (k_begin >= S) return;                   // whole wavefront: segment past this fan's depth
+    const int k_end = min(S, k_begin + seg);
     PhysArgs p{};
     p.atten = 2;
     Ray ray;
@@ -1137,16 +1145,16 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
     float zn[kScatterSpl];
 #pragma unroll
     for (int q = 0; q < kScatterSpl; ++q) {
-        const int k = ch * kScatterSpl + q;
-        zn[q] = (ray_ok && k < S) ? zrow[k] : 0.0f;
+        const int k = k_begin + ch * kScatterSpl + q;
+        zn[q] = (ray_ok && k < k_end) ? zrow[k] : 0.0f;
     }
-    for (int k0 = 0; k0 < S; k0 += G) {
+    for (int k0 = k_begin; k0 < k_end; k0 += G) {
         float zb[kScatterSpl];
 #pragma unroll
         for (int q = 0; q < kScatterSpl; ++q) {
             zb[q] = zn[q];
             const int k = k0 + G + ch * kScatterSpl + q;
-            zn[q] = (ray_ok && k < S) ? zrow[k] : 0.0f;
+            zn[q] = (ray_ok && k < k_end) ? zrow[k] : 0.0f;
         }
         Stencil st[kScatterSpl];
         int qf = -1, ql = -1;
@@ -1669,17 +1677,28 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
     // two wavefronts per SIMD; then two (more wavefronts, each walking a
     // quarter as many groups)
     if (scatter_rays == 0) scatter_rays = (t.total_rays / 8 < 2048) ? 2 : 8;
-    int blocks = 0;
-    for (int f = 0; f < t.n; ++f) blocks += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
+    int blocks = 0, smax = 0;
+    for (int f = 0; f < t.n; ++f) {
+        blocks += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
+        smax = std::max(smax, t.f[f].n_samples);
+    }
+    if (blocks <= 0 || smax <= 0) return hipSuccess;
+    // depth segments: enough wavefronts to fill the GPU (>= 8192), each
+    // segment a whole number of groups
+    const int G = 256 / scatter_rays;
+    const int ngroups = (smax + G - 1) / G;
+    const int nseg = std::max(1, std::min(ngroups, (8192 + blocks - 1) / blocks));
+    const int seg = ((ngroups + nseg - 1) / nseg) * G;
+    const dim3 grid(blocks, (smax + seg - 1) / seg);
     switch (scatter_rays) {
     case 2:
-        hipLaunchKernelGGL((k_scatter<2>), dim3(blocks), dim3(64), 0, st, v, t, poses, zbar, gZ, xcd_group);
+        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, t, poses, zbar, gZ, seg, xcd_group);
         break;
     case 4:
-        hipLaunchKernelGGL((k_scatter<4>), dim3(blocks), dim3(64), 0, st, v, t, poses, zbar, gZ, xcd_group);
+        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, t, poses, zbar, gZ, seg, xcd_group);
         break;
     case 8:
-        hipLaunchKernelGGL((k_scatter<8>), dim3(blocks), dim3(64), 0, st, v, t, poses, zbar, gZ, xcd_group);
+        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, t, poses, zbar, gZ, seg, xcd_group);
         break;
     default:
         return hipErrorInvalidValue;
