@@ -96,11 +96,6 @@ __device__ __forceinline__ double div64(double a, double b)
 #ifndef GATHER_UNROLL
 #define GATHER_UNROLL 2
 #endif
-// the adjoint's per-lane walks run one interface per iteration: unrolling
-// them only raises register pressure
-#ifndef WALK_UNROLL
-#define WALK_UNROLL 1
-#endif
 
 // LDS index padding: doubles (one pad word per 16) and floats (per 32)
 __device__ __forceinline__ int pad8(int i) { return i + (i >> 4); }
@@ -705,6 +700,8 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     constexpr int kMaxTiles = (DUS_MAX_SAMPLES + T - 1) / T;
     static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
     constexpr int NB = T / kCarryBlock;
+    // walks unrolled where the registers allow three wavefronts per SIMD
+    constexpr int kWalkUnroll = (C <= 4 && !SPK && !FUSED) ? C : 1;
     __shared__ float s_g[3 * T];     // dZ/du of every sample of the tile
     __shared__ double s_rho[T + T / 16];
     __shared__ double s_z[T + T / 16];
@@ -861,44 +858,43 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             double v0 = v0s, v1 = v1s, D = Ds, w1 = w1s;
             Mat QL{1.0, 0.0, 0.0, 1.0};
             double qdl = 1.0;
-#pragma unroll WALK_UNROLL
+            // branch-free: an interface outside [1, S) has rho = 0 (gather)
+            // and the identity map, so its step leaves the state unchanged and
+            // forces nothing (pixel 0 is zero; the loss still counts it)
+#pragma unroll kWalkUnroll
             for (int i = 0; i < C; ++i) {
                 const int k = t0 + base + i;
-                if (k >= 1 && k < S) {
-                    const double r = s_rho[pad8(base + i)];
-                    const Map m = make_map(r, a2, sgn, true);
-                    const double v1n = fma(v0, r, v1);
-                    const double w1p = rcp64(v1n);
-                    const double e = r * D * w1 * w1p;
-                    double eb;
-                    if (FUSED) {
-                        const double gn = s_gain[pad4(base + i)];
-                        const double diff = e * gn - (double)s_eb[pad4(base + i)];
-                        loss += diff * diff * inv_npix;
-                        eb = 2.0 * diff * inv_npix * gn;
-                        s_eb[pad4(base + i)] = (float)eb;
-                    } else {
-                        eb = s_eb[pad4(base + i)];
-                    }
-                    const double f0 = -eb * e * r * w1p;
-                    const double f1 = -eb * e * (w1 + w1p);
-                    const double fD = eb * r * w1 * w1p;
-                    f.l0 = fma(f0, QL.a, fma(f1, QL.b, f.l0));
-                    f.l1 = fma(f0, QL.c, fma(f1, QL.d, f.l1));
-                    f.lD = fma(fD, qdl, f.lD);
-                    const double n00 = fma(QL.a, m.m00, QL.b * m.m10), n01 = fma(QL.a, r, QL.b);
-                    const double n10 = fma(QL.c, m.m00, QL.d * m.m10), n11 = fma(QL.c, r, QL.d);
-                    QL = Mat{n00, n01, n10, n11};
-                    qdl *= m.det;
-                    const double v0n = fma(v0, m.m00, v1 * m.m10);
-                    v0 = v0n;
-                    v1 = v1n;
-                    w1 = w1p;
-                    D *= m.det;
-                } else if (FUSED && k == 0) {
-                    const double diff = -(double)s_eb[pad4(base + i)];
+                const bool valid = (k >= 1) && (k < S);
+                const double r = s_rho[pad8(base + i)];
+                const Map m = make_map(r, a2, sgn, valid);
+                const double v1n = fma(v0, r, v1);
+                const double w1p = rcp64(v1n);
+                const double e = r * D * w1 * w1p;
+                double eb;
+                if (FUSED) {
+                    const double gn = s_gain[pad4(base + i)];
+                    const double diff = e * gn - (double)s_eb[pad4(base + i)];
                     loss += diff * diff * inv_npix;
+                    eb = 2.0 * diff * inv_npix * gn;
+                    s_eb[pad4(base + i)] = (float)eb;
+                } else {
+                    eb = s_eb[pad4(base + i)];
                 }
+                const double f0 = -eb * e * r * w1p;
+                const double f1 = -eb * e * (w1 + w1p);
+                const double fD = eb * r * w1 * w1p;
+                f.l0 = fma(f0, QL.a, fma(f1, QL.b, f.l0));
+                f.l1 = fma(f0, QL.c, fma(f1, QL.d, f.l1));
+                f.lD = fma(fD, qdl, f.lD);
+                const double n00 = fma(QL.a, m.m00, QL.b * m.m10), n01 = fma(QL.a, r, QL.b);
+                const double n10 = fma(QL.c, m.m00, QL.d * m.m10), n11 = fma(QL.c, r, QL.d);
+                QL = Mat{n00, n01, n10, n11};
+                qdl *= m.det;
+                const double v0n = fma(v0, m.m00, v1 * m.m10);
+                v0 = v0n;
+                v1 = v1n;
+                w1 = w1p;
+                D *= m.det;
             }
         }
         // suffix composition over lanes: Psi_l = Phi_l o Phi_{l+1} o ... o Phi_63
@@ -956,13 +952,14 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         // and gives dL/drho_i (adj_rbar).
         {
             double v0 = v0s, v1 = v1s, D = Ds, w1 = w1s;
-#pragma unroll WALK_UNROLL
+#pragma unroll kWalkUnroll
             for (int i = 0; i < C; ++i) {
                 const int k = t0 + base + i;
+                const bool valid = (k >= 1) && (k < S);
                 double qz = 0.0;
-                if (k >= 1 && k < S) {
+                {   // branch-free, as walk 1 (dq = 0 outside [1, S))
                     const double r = s_rho[pad8(base + i)];
-                    const Map m = make_map(r, a2, sgn, true);
+                    const Map m = make_map(r, a2, sgn, valid);
                     const double v1n = fma(v0, r, v1);
                     const double w1p = rcp64(v1n);
                     const double e = r * D * w1 * w1p;
