@@ -409,8 +409,12 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
         double zm = __shfl_up(z, 1);
         if (lane == 0) zm = zprev;
         zprev = lane_read(z, 63);
-        double rho = 0.0, dq = 0.0;
-        if (k >= 1 && k < S) rho = iface_rho(zm, z, absm, KEEPZ ? &dq : nullptr);
+        // interface (k-1, k); outside [1, S) rho = 0 and dq = 0
+        const bool ok = (k >= 1) && (k < S);
+        double dq = 0.0;
+        double rho = iface_rho(zm, z, absm, KEEPZ ? &dq : nullptr);
+        rho = ok ? rho : 0.0;
+        dq = ok ? dq : 0.0;
         s_rho[pad8(i)] = rho;
         if (KEEPZ) {
             s_z[pad8(i)] = z;
@@ -418,9 +422,16 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
         }
         if (s_zc && lane == 63 && (jj & 3) == 3) s_zc[jj >> 2] = z;
         if (KEEPG) {
-            s_g[i] = (float)gu[0];
-            s_g[T + i] = (float)gu[1];
-            s_g[2 * T + i] = (float)gu[2];
+            // dZ/dp per mm: dZ/du / h, zero along an axis where the sample
+            // lies outside the volume (clamped)
+            const double kk = (double)min(k, S - 1);
+            const int n[3] = {v.nx, v.ny, v.nz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double u = fma(kk, ray.du[a], ray.u0[a]);
+                const bool inside = (u >= 0.0) && (u <= (double)(n[a] - 1));
+                s_g[a * T + i] = inside ? (float)(gu[a] / (double)v.h[a]) : 0.0f;
+            }
         }
     }
 }
@@ -601,20 +612,19 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
         double D = cD * xd;
 #pragma unroll
         for (int i = 0; i < C; ++i) {
+            // branch-free: outside [1, S) rho = 0 and the map is the identity,
+            // so the pixel is 0 and the state unchanged
             const int k = t0 + base + i;
             const bool valid = (k >= 1) && (k < S);
-            float pix = 0.0f;
-            if (valid) {
-                const double r = s_rho[pad8(base + i)];
-                const Map m = make_map(r, a2, sgn, true);
-                const double v1n = fma(v0, r, v1);
-                pix = (float)(r * D * rcp64(v1 * v1n));
-                if (want_piv) piv = fmin(piv, fabs(v1n * rcp64(v1)));
-                const double v0n = fma(v0, m.m00, v1 * m.m10);
-                v0 = v0n;
-                v1 = v1n;
-                D *= m.det;
-            }
+            const double r = s_rho[pad8(base + i)];
+            const Map m = make_map(r, a2, sgn, valid);
+            const double v1n = fma(v0, r, v1);
+            const float pix = (float)(r * D * rcp64(v1 * v1n));
+            if (want_piv) piv = valid ? fmin(piv, fabs(v1n * rcp64(v1))) : piv;
+            const double v0n = fma(v0, m.m00, v1 * m.m10);
+            v0 = v0n;
+            v1 = v1n;
+            D *= m.det;
             s_pix[pad4(base + i)] = pix;
         }
         // carry to the next tile, renormalised by a power of two
@@ -791,7 +801,6 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     double z_next = 0.0;           // first sample of the next tile
     double loss = 0.0;
     double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
-    const double ih[3] = {1.0 / (double)v.h[0], 1.0 / (double)v.h[1], 1.0 / (double)v.h[2]};
     for (int t = ntiles - 1; t >= 0; --t) {
         const int t0 = t * T;
         const double c0 = s_carry[t][0], c1 = s_carry[t][1], cD = s_carry[t][2];
@@ -999,33 +1008,26 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         }
         __syncthreads();
 
-        // dL/dZ_k per sample (rho depends on the samples on both sides)
+        // dL/dZ_k per sample (rho depends on the samples on both sides):
+        // sample k is the right end of interface k-1 and the left end of
+        // interface k.  Branch-free: the interface factors vanish outside
+        // [1, S), so dL/dZ is zero for k >= S and only the store is guarded.
 #pragma unroll 1
         for (int jj = 0; jj < C; ++jj) {
             const int i = jj * 64 + lane;
             const int k = t0 + i;
-            if (k >= S) continue;
-            // sample k is the right end of interface k-1 and the left end of
-            // interface k
             const double zl = (i > 0) ? s_z[pad8(i - 1)] : zstart;
             const double zr = (i + 1 < T) ? s_z[pad8(i + 1)] : z_next;
-            const double ql = (k >= 1) ? s_rho[pad8(i)] : 0.0;
+            const double ql = s_rho[pad8(i)];
             const double qr = (k + 1 < S) ? ((i + 1 < T) ? s_rho[pad8(i + 1)] : rbar_next) : 0.0;
-            double zb = 0.0;
-            if (ql != 0.0) zb = ql * zl;
-            if (qr != 0.0) zb = fma(-qr, zr, zb);
-            zbar[obase + k] = (float)zb;
-            if (pose_acc && zb != 0.0) {
-                // dL/dp = zb dZ/du / h per axis (0 where the sample is clamped);
-                // dL/dR accumulates (s_k dir) outer dL/dp
-                const double kk = (double)k;
-                const double sk = fma(kk, ray.ds, ray.r0);
-                const int n[3] = {v.nx, v.ny, v.nz};
+            const double zb = fma(-qr, zr, ql * zl);
+            if (k < S) zbar[obase + k] = (float)zb;
+            if (pose_acc) {
+                // dL/dp = zb dZ/dp; dL/dR accumulates (s_k dir) outer dL/dp
+                const double sk = fma((double)k, ray.ds, ray.r0);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const double u = fma(kk, ray.du[a], ray.u0[a]);
-                    const bool inside = (u >= 0.0) && (u <= (double)(n[a] - 1));
-                    const double gp = inside ? zb * (double)s_g[a * T + i] * ih[a] : 0.0;
+                    const double gp = zb * (double)s_g[a * T + i];
                     gsum[a] += gp;
                     gssum[a] = fma(sk, gp, gssum[a]);
                 }
