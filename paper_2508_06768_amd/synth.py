@@ -281,14 +281,15 @@ def case_batched_c2(B: int = 64, seed: int = 1006, vol_seed: int = 1002) -> Case
                 effects_physics(seed), extra={"target_poses": tgt})
 
 
-def case_registration(seed: int = 1005, n: int = 512, P: int = 32) -> Case:
+def case_registration(seed: int = 1005, n: int = 512, P: int = 32, offset: float = 10.0) -> Case:
     """512^3 volume at 0.5 mm (noise sigma 4 voxels), 32 ground-truth poses,
-    initial poses +-10 mm / +-10 deg, 384 rays x 1536 samples, 70 deg, 192 mm."""
+    initial poses +-offset mm / +-offset deg (10 by default), 384 rays x 1536
+    samples, 70 deg, 192 mm."""
     h = 255.5 / (n - 1)
     Z = brain_volume(seed, n, h, noise_sigma_vox=4.0)
     rng = np.random.default_rng(seed)
     gt = random_poses(rng, P, (n - 1) * h)
-    init = offset_poses(rng, gt, 10.0, 10.0)
+    init = offset_poses(rng, gt, offset, offset)
     fans = [FanSpec(384, 1536, 70 * DEG, 192.0 / 1536, 0.0, p) for p in range(P)]
     return Case(f"registration_{n}cube_{P}poses", Z, (h,) * 3, (0.0,) * 3, init, fans,
                 effects_physics(seed), extra={"gt_poses": gt})
