@@ -1365,6 +1365,7 @@ __global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const fl
     const bool active = (k < S) && (j0 < n);
     const long long col = fr.out_offset + k;
     const double inv_npix = 1.0 / ((double)n * (double)S);
+    const float two_inv_npix = (float)(2.0 * inv_npix);
     double lsum = 0.0;
     if (active) {
         float x[W];
@@ -1412,10 +1413,12 @@ __global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const fl
             }
             const long long oidx = col + (long long)j * S;
             if (MODE == 2) {
-                const double dd = (double)acc - (double)tg[o];
+                // residual in FP32 (one rounding of the difference of two
+                // floats); its square summed in FP64, scaled once at the end
+                const float d = acc - tg[o];
                 if (image) image[oidx] = acc;
-                out[oidx] = (float)(2.0 * dd * inv_npix);
-                lsum += dd * dd * inv_npix;
+                out[oidx] = d * two_inv_npix;
+                lsum += (double)(d * d);
             } else {
                 out[oidx] = acc;
             }
@@ -1424,7 +1427,7 @@ __global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const fl
     if (MODE == 2 && loss_acc) {
         // one partial per block, summed by k_sum_f64 (no contended atomics)
         __shared__ double s_part[4];
-        lsum = wave_sum(lsum);
+        lsum = wave_sum(lsum) * inv_npix;
         if (lane == 0) s_part[wv] = lsum;
         __syncthreads();
         if (tid == 0) loss_acc[b] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
