@@ -482,7 +482,8 @@ __device__ __forceinline__ void chunk_product(const double *s_rho, int base, int
 {
     Q = Mat{1.0, 0.0, 0.0, 1.0};
     qd = 1.0;
-#pragma unroll 1
+    // unrolled: the C LDS reads issue together
+#pragma unroll
     for (int i = 0; i < C; ++i) {
         const int k = t0 + base + i;
         const bool valid = (k >= 1) && (k < S);
