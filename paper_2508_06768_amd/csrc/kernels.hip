@@ -1089,6 +1089,12 @@ struct ScatterBox {
     static constexpr int cap = RB == 2 ? 4096 : (RB == 4 ? 2048 : 1024);   // 64-bit entries
 };
 
+// x 2^F rounded to the nearest integer; requires |x| 2^F < 2^62
+__device__ __forceinline__ long long to_fixed(float x, int F)
+{
+    return __double2ll_rn(ldexp((double)x, F));
+}
+
 // largest biased FP32 exponent over the wavefront (bitwise, by ballots)
 __device__ __forceinline__ int wave_max_exp(int e)
 {
@@ -1238,8 +1244,7 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
                         if (ra[c] != 0.0f)
-                            atomicAdd(&s_box[cur + off[c]],
-                                      (unsigned long long)__double2ll_rn(ldexp((double)ra[c], F)));
+                            atomicAdd(&s_box[cur + off[c]], (unsigned long long)to_fixed(ra[c], F));
                         ra[c] = 0.0f;
                     }
                 }
@@ -1259,39 +1264,43 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
                     if (ra[c] != 0.0f)
-                        atomicAdd(&s_box[cur + off[c]], (unsigned long long)__double2ll_rn(ldexp((double)ra[c], F)));
+                        atomicAdd(&s_box[cur + off[c]], (unsigned long long)to_fixed(ra[c], F));
             }
         }
         __syncthreads();
-        // flush: lanes cover (row, x) pairs, consecutive lanes on consecutive
-        // x; four rows' LDS reads are issued before their atomics
-        int lg2 = 0;
-        while ((1 << lg2) < bx) ++lg2;
-        const int rows_per = 64 >> lg2;
-        const int xl = lane & ((1 << lg2) - 1), sub = lane >> lg2;
-        const int nrows = by * bz;
-        if (xl < bx) {
-            for (int r0 = sub; r0 < nrows; r0 += 4 * rows_per) {
+        // flush: the box's entries in x-fastest order, 64 consecutive entries
+        // per pass (consecutive lanes on consecutive x of a row); a lane's
+        // (x, y, z) advances by constant carries, and four entries' LDS reads
+        // are issued before their atomics
+        {
+            const int E = bx * by * bz;
+            const int dx = 64 % bx, dyz = 64 / bx;
+            const int dy = dyz % by, dz = dyz / by;
+            int x = lane % bx, y = (lane / bx) % by, z = lane / (bx * by);
+            for (int e0 = 0; e0 < E; e0 += 256) {
                 unsigned long long val[4];
                 int at[4], gi[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int row = r0 + u * rows_per;
                     val[u] = 0ull;
                     at[u] = gi[u] = 0;
-                    if (row < nrows) {
-                        const int zz = row / by, yy = row - zz * by;
-                        at[u] = zz * ps + yy * rs + xl;
-                        gi[u] = ((oz + zz) * v.ny + (oy + yy)) * v.nx + (ox + xl);
+                    if (e0 + 64 * u + lane < E) {
+                        at[u] = z * ps + y * rs + x;
+                        gi[u] = ((oz + z) * v.ny + (oy + y)) * v.nx + (ox + x);
                         val[u] = s_box[at[u]];
                     }
+                    x += dx;
+                    y += dy;
+                    z += dz;
+                    if (x >= bx) { x -= bx; ++y; }
+                    if (y >= by) { y -= by; ++z; }
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (val[u] != 0ull) {
                         s_box[at[u]] = 0ull;
-                        const float x = (float)ldexp((double)(long long)val[u], -F);
-                        if (x != 0.0f) atomicAdd(gZ + gi[u], x);
+                        const float xv = (float)ldexp((double)(long long)val[u], -F);
+                        if (xv != 0.0f) atomicAdd(gZ + gi[u], xv);
                     }
                 }
             }
