@@ -77,13 +77,32 @@ def rel_l2(a, b) -> float:
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
 
 
-def parity_report(gpu, ref) -> dict:
-    gpu = np.asarray(gpu, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+def parity_report(gpu, ref, fans=None) -> dict:
+    """The parity metric: image relative l2 (the bar), max |error| over
+    max |image|, the largest relative error on pixels above 1 % of the
+    maximum, and (given the fans in packing order) the per-ray relative l2,
+    p99 and max over rays with a non-zero reference."""
+    gpu = np.asarray(gpu, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
     m = np.abs(ref).max() if ref.size else 0.0
     big = np.abs(ref) > 0.01 * m
-    return {
+    rep = {
         "rel_l2": rel_l2(gpu, ref),
         "max_abs_over_max": float(np.abs(gpu - ref).max() / m) if m > 0 else float(np.abs(gpu - ref).max()),
         "max_rel_big": float(np.max(np.abs(gpu[big] - ref[big]) / np.abs(ref[big]))) if big.any() else 0.0,
     }
+    if fans is not None:
+        per_ray = []
+        off = 0
+        for f in fans:
+            n = f.n_rays * f.n_samples
+            g = gpu[off:off + n].reshape(f.n_rays, f.n_samples)
+            r = ref[off:off + n].reshape(f.n_rays, f.n_samples)
+            nr = np.linalg.norm(r, axis=1)
+            ok = nr > 0
+            per_ray.extend(list(np.linalg.norm(g - r, axis=1)[ok] / nr[ok]))
+            off += n
+        if per_ray:
+            rep["ray_rel_l2_p99"] = float(np.percentile(per_ray, 99))
+            rep["ray_rel_l2_max"] = float(np.max(per_ray))
+    return rep

@@ -55,8 +55,8 @@ def coarse_case(seed=5) -> synth.Case:
     return synth.Case("coarse40", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans, ph)
 
 
-def _check_images(gpu, ref, tag):
-    rep = H.parity_report(gpu, ref)
+def _check_images(gpu, ref, tag, fans=None):
+    rep = H.parity_report(gpu, ref, fans)
     print(tag, rep, flush=True)
     assert rep["rel_l2"] <= RTOL_IMG, rep
     assert rep["max_abs_over_max"] <= RTOL_IMG, rep
@@ -98,7 +98,7 @@ def test_forward_parity_ragged(refl, atten, effects):
     geom, Z, poses = _gpu(case)
     img, piv = render(Z, poses, geom, want_pivot=True)
     ref, rpiv = H.oracle_render(case, want_pivot=True)
-    _check_images(img.cpu().numpy(), ref, f"ragged refl={refl} atten={atten} fx={effects}")
+    _check_images(img.cpu().numpy(), ref, f"ragged refl={refl} atten={atten} fx={effects}", case.fans)
     np.testing.assert_allclose(piv.cpu().numpy(), rpiv, rtol=1e-5)
 
 
@@ -109,7 +109,7 @@ def test_forward_parity_phantom():
     geom, Z, poses = _gpu(case)
     img, piv = render(Z, poses, geom, want_pivot=True)
     ref, rpiv = H.oracle_render(case, want_pivot=True)
-    _check_images(img.cpu().numpy(), ref, "phantom64")
+    _check_images(img.cpu().numpy(), ref, "phantom64", case.fans)
     np.testing.assert_allclose(piv.cpu().numpy(), rpiv, rtol=1e-5)
 
 
@@ -171,7 +171,7 @@ def test_fused_plan_matches_oracle():
             grad[off:off + n] = 2 * d / n
             off += n
         rV, rp = H.oracle_backward(case, grad)
-        _check_images(bm.cpu().numpy(), img, f"plan image fx={effects}")
+        _check_images(bm.cpu().numpy(), img, f"plan image fx={effects}", case.fans)
         assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
         e = H.rel_l2(gZ.cpu().numpy(), rV)
         print("plan dZ rel l2", e, flush=True)

@@ -40,7 +40,7 @@ def test_adjoint_full_size_vs_oracle_and_finite_differences():
     tf = target.astype(np.float32).astype(np.float64)
     img = render(Z, P, geom)
     ref = H.oracle_render(case)
-    rep = H.parity_report(img.cpu().numpy(), ref)
+    rep = H.parity_report(img.cpu().numpy(), ref, case.fans)
     print("forward", rep, flush=True)
     assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
     # MSE gradient of the GPU image, adjoint on the GPU
