@@ -1089,10 +1089,17 @@ struct ScatterBox {
     static constexpr int cap = RB == 2 ? 4096 : (RB == 4 ? 2048 : 1024);   // 64-bit entries
 };
 
-// x 2^F rounded to the nearest integer; requires |x| 2^F < 2^62
+// x 2^F rounded to the nearest integer; requires |x| 2^F < 2^62.  All in
+// FP32 and exact: y = rint(|x| 2^F) is an integer with at most 24
+// significant bits, hi = floor(y 2^-32), and lo = y - hi 2^32 in [0, 2^32)
+// keeps only bits of y (no rounding); the magnitude is hi 2^32 + lo.
 __device__ __forceinline__ long long to_fixed(float x, int F)
 {
-    return __double2ll_rn(ldexp((double)x, F));
+    const float y = __builtin_rintf(ldexpf(fabsf(x), F));
+    const float hi = floorf(y * 0x1p-32f);
+    const float lo = fmaf(-hi, 0x1p32f, y);
+    const long long mag = (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+    return (x < 0.0f) ? -mag : mag;
 }
 
 // largest biased FP32 exponent over the wavefront (bitwise, by ballots)
