@@ -223,6 +223,19 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"])
     log(f"bench: kernels {json.dumps(kern)} footprint voxels {vfp}")
 
+    # display and ablation modes: sampling-only render of the whole batch,
+    # scan conversion of one fan onto 512 x 512 pixels
+    from paper_2508_06768_amd.render import sample_volume, scan_convert
+    samp = torch.empty(N, device=dev)
+    ms_samp = timed(lambda: sample_volume(Z, poses, geom, out=samp), 10, ev)
+    render(Z, poses, geom, out=out, ws=ws_f)
+    depth = case.fans[0].r0 + case.fans[0].n_samples * case.fans[0].ds
+    half = depth * np.sin(case.fans[0].aperture / 2)
+    ms_scan = timed(lambda: scan_convert(out, geom, 0, 512, 512, -half, 0.0, 2 * half / 511, depth / 511), 10, ev)
+    modes = {"sampling_only": {"ms": ms_samp, "value": N / (ms_samp * 1e-3)},
+             "scan_convert_512x512": {"ms": ms_scan}}
+    log(f"bench: modes {json.dumps(modes)}")
+
     if args.calib_copy:
         src = torch.empty(CALIB_BYTES // 4, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -259,6 +272,7 @@ def main():
         "plain_per_pose": None if plain_ms is None else {"ms": plain_ms, "value": N / (plain_ms * 1e-3)},
         "plain_forward_per_pose": (None if plain_fwd_ms is None
                                    else {"ms": plain_fwd_ms, "value": N / (plain_fwd_ms * 1e-3)}),
+        "modes": modes,
         "phases_ms": phases,
         "kernels": kern,
         "roofline": {

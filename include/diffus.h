@@ -164,6 +164,38 @@ int dus_philox4x32_10(const uint32_t *counters, int64_t n, uint64_t seed, uint32
 int dus_pixel_gain(const dus_fan *fan, const dus_physics *phys, float *out, void *stream);
 
 /*
+ * Sampling-only render (the "sampling" row of Table 1, Sec. 3): pixel k of
+ * ray j is the impedance at the ray sample itself (trilinear, clamp-to-edge,
+ * the positions of dus_render_bmode), with no reflection, attenuation,
+ * speckle or blur.  Same arguments and image layout as dus_render_bmode;
+ * out: device FP32.  Needs no workspace.
+ */
+int dus_sample_volume(const float *Z, const dus_volume *vol, const float *poses, const dus_fan *fans,
+                      int32_t n_poses, float *out, void *stream);
+
+/*
+ * Scan conversion for display (the fan images of Fig. 3): the polar image of
+ * one fan (rows = rays at angles -A/2 .. A/2, columns = depths r0 + k ds) is
+ * resampled onto a Cartesian grid in the probe's x-z plane.  Output pixel
+ * (iz, ix) sits at x = x0 + ix dx, z = z0 + iz dz (mm, probe frame: x
+ * lateral, z along the beam axis); with r = |(x, z)| and theta = atan2(x, z)
+ * its polar indices are j = (theta + A/2)(n_rays - 1)/A and k = (r - r0)/ds,
+ * and its value is the bilinear interpolation of the polar image (along
+ * depth, then along the rays) for 0 <= j <= n_rays - 1 and
+ * 0 <= k <= n_samples - 1, else `fill`.  Needs n_rays >= 2, n_samples >= 2.
+ *   bmode  device FP32, the fan's image at fan->out_offset
+ *   out    device FP32 [nz][nx]
+ */
+typedef struct {
+    int32_t nx, nz;          /* output pixels along x and z */
+    float x0_mm, z0_mm;      /* position of pixel (0, 0) */
+    float dx_mm, dz_mm;      /* pixel pitch (> 0) */
+    float fill;              /* value outside the fan */
+} dus_grid2d;
+
+int dus_scan_convert(const float *bmode, const dus_fan *fan, const dus_grid2d *grid, float *out, void *stream);
+
+/*
  * Footprint of the rendering: mask[v] = 1 for every voxel v that is a corner
  * of the trilinear stencil of some sample of some ray (other entries are left
  * untouched).  mask: device uint8 [nz][ny][nx].  Used to count the distinct

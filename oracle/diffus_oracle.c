@@ -512,6 +512,39 @@ int orc_blur_radius(const orc_physics *ph, int S, int k)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Display: scan conversion of one fan's polar image (rows = rays at angles */
+/* -A/2 .. A/2, columns = depths r0 + k ds) onto a Cartesian grid of the    */
+/* probe's x-z plane, as in the fan images of Fig. 3.  Pixel (iz, ix) sits  */
+/* at x = x0 + ix dx, z = z0 + iz dz; its polar indices are                 */
+/*   j = (atan2(x, z) + A/2)(n_r - 1)/A,   k = (|(x, z)| - r0)/ds,          */
+/* and its value is the bilinear interpolation of the image (along depth,   */
+/* then along the rays) inside 0 <= j <= n_r-1, 0 <= k <= S-1, else fill.   */
+/* ------------------------------------------------------------------------ */
+void orc_scan_convert(const double *img, int n_r, int S, double A, double r0, double ds,
+                      int nx, int nz, double x0, double z0, double dx, double dz, double fill,
+                      double *out)
+{
+    for (int iz = 0; iz < nz; ++iz)
+        for (int ix = 0; ix < nx; ++ix) {
+            const double x = x0 + ix * dx, z = z0 + iz * dz;
+            const double r = sqrt(x * x + z * z), th = atan2(x, z);
+            const double j = (th + 0.5 * A) * (n_r - 1) / A, k = (r - r0) / ds;
+            double v = fill;
+            if (j >= 0.0 && j <= n_r - 1 && k >= 0.0 && k <= S - 1) {
+                int j0 = (int)floor(j), k0 = (int)floor(k);
+                if (j0 > n_r - 2) j0 = n_r - 2;
+                if (k0 > S - 2) k0 = S - 2;
+                const double fj = j - j0, fk = k - k0;
+                const double *p0 = img + (size_t)j0 * S + k0, *p1 = p0 + S;
+                const double a = p0[0] + fk * (p0[1] - p0[0]);
+                const double b = p1[0] + fk * (p1[1] - p1[0]);
+                v = a + fj * (b - a);
+            }
+            out[(size_t)iz * nx + ix] = v;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole fan: raw echoes, gains, blur.                                      */
 /*   solver 0: O(S) transfer form;  1: literal O(S^2) progressive solve.     */
 /* img [n_rays][S]; raw (nullable) receives the pre-effect echoes e;         */

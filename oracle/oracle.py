@@ -228,6 +228,26 @@ def ray_samples(vol: Volume, pose, fan: Fan, j: int, want_grad: bool = False):
     return Zs
 
 
+def sample_image(vol: Volume, pose, fan: Fan) -> np.ndarray:
+    """Sampling-only image [n_rays][n_samples]: the impedance at every ray
+    sample (the ablation row of Table 1)."""
+    return np.stack([ray_samples(vol, pose, fan, j) for j in range(fan.n_rays)]) if fan.n_rays else \
+        np.zeros((0, fan.n_samples))
+
+
+def scan_convert(img, fan: Fan, nx: int, nz: int, x0: float, z0: float, dx: float, dz: float,
+                 fill: float = 0.0) -> np.ndarray:
+    """One fan's polar image [n_rays][n_samples] on an nz x nx Cartesian grid
+    of the probe's x-z plane (bilinear; `fill` outside the fan)."""
+    im = np.ascontiguousarray(np.asarray(img, dtype=np.float64).reshape(fan.n_rays, fan.n_samples))
+    out = np.zeros((nz, nx))
+    lib().orc_scan_convert(_dp(im), ctypes.c_int(fan.n_rays), ctypes.c_int(fan.n_samples),
+                           ctypes.c_double(fan.aperture), ctypes.c_double(fan.r0), ctypes.c_double(fan.ds),
+                           ctypes.c_int(nx), ctypes.c_int(nz), ctypes.c_double(x0), ctypes.c_double(z0),
+                           ctypes.c_double(dx), ctypes.c_double(dz), ctypes.c_double(fill), _dp(out))
+    return out
+
+
 def sample(vol: Volume, u):
     L = lib()
     uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(3))

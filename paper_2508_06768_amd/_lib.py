@@ -46,6 +46,11 @@ class DusSchedule(ctypes.Structure):
     _fields_ = [("fwd_chunk", c_i32), ("bwd_chunk", c_i32), ("xcd_group", c_i32), ("scatter_rays", c_i32)]
 
 
+class DusGrid2d(ctypes.Structure):
+    _fields_ = [("nx", c_i32), ("nz", c_i32), ("x0_mm", ctypes.c_float), ("z0_mm", ctypes.c_float),
+                ("dx_mm", ctypes.c_float), ("dz_mm", ctypes.c_float), ("fill", ctypes.c_float)]
+
+
 # every symbol include/diffus.h declares, with (restype, argtypes)
 SIGNATURES = {
     "dus_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -60,6 +65,9 @@ SIGNATURES = {
                                                  c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "dus_philox4x32_10": (ctypes.c_int, [c_vp, c_i64, c_u64, c_vp, c_vp]),
     "dus_pixel_gain": (ctypes.c_int, [ctypes.POINTER(DusFan), ctypes.POINTER(DusPhysics), c_vp, c_vp]),
+    "dus_sample_volume": (ctypes.c_int, [c_vp, ctypes.POINTER(DusVolume), c_vp, ctypes.POINTER(DusFan), c_i32,
+                                         c_vp, c_vp]),
+    "dus_scan_convert": (ctypes.c_int, [c_vp, ctypes.POINTER(DusFan), ctypes.POINTER(DusGrid2d), c_vp, c_vp]),
     "dus_footprint_mask": (ctypes.c_int, [ctypes.POINTER(DusVolume), c_vp, ctypes.POINTER(DusFan), c_i32,
                                           c_vp, c_vp]),
     "dus_set_schedule": (ctypes.c_int, [ctypes.POINTER(DusSchedule)]),

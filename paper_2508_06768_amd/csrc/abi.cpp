@@ -482,6 +482,42 @@ int dus_footprint_mask(const dus_volume *vol, const float *poses, const dus_fan 
     return DUS_OK;
 }
 
+int dus_sample_volume(const float *Z, const dus_volume *vol, const float *poses, const dus_fan *fans,
+                      int32_t n_poses, float *out, void *stream)
+{
+    int s;
+    if ((s = check_volume(vol)) != DUS_OK) return s;
+    if ((s = check_fans(fans, n_poses)) != DUS_OK) return s;
+    if (image_extent(fans, n_poses) == 0) return DUS_OK;
+    if (!Z || !poses || !out) return fail(DUS_EINVAL, "NULL pointer");
+    const dus::VolArgs va = vol_args(Z, vol);
+    for (const auto &t : build_tables(fans, n_poses))
+        DUS_HIP(dus::launch_sample(g_sched.xcd_group, va, t, poses, out, reinterpret_cast<hipStream_t>(stream)),
+                "sample kernel launch");
+    return DUS_OK;
+}
+
+int dus_scan_convert(const float *bmode, const dus_fan *fan, const dus_grid2d *grid, float *out, void *stream)
+{
+    if (!fan || !grid) return fail(DUS_EINVAL, "fan and grid are required");
+    int s;
+    if ((s = check_fans(fan, 1)) != DUS_OK) return s;
+    if (fan->n_rays < 2 || fan->n_samples < 2) return fail(DUS_ESHAPE, "scan conversion needs n_rays >= 2 and n_samples >= 2");
+    if (!(fan->aperture_rad > 0.0f)) return fail(DUS_EINVAL, "scan conversion needs aperture_rad > 0");
+    if (grid->nx < 0 || grid->nz < 0) return fail(DUS_ESHAPE, "grid nx, nz must be >= 0");
+    if ((int64_t)grid->nx * grid->nz > ((int64_t)1 << 31)) return fail(DUS_ESHAPE, "grid too large");
+    if (!(grid->dx_mm > 0.0f) || !(grid->dz_mm > 0.0f) || !finite_f(grid->dx_mm) || !finite_f(grid->dz_mm) ||
+        !finite_f(grid->x0_mm) || !finite_f(grid->z0_mm))
+        return fail(DUS_EINVAL, "grid pitch must be finite and > 0, origin finite");
+    if ((int64_t)grid->nx * grid->nz == 0) return DUS_OK;
+    if (!bmode || !out) return fail(DUS_EINVAL, "NULL pointer");
+    DUS_HIP(dus::launch_scan_convert(bmode + fan->out_offset, fan->n_rays, fan->n_samples, fan->aperture_rad, fan->r0_mm,
+                                     fan->ds_mm, grid->nx, grid->nz, grid->x0_mm, grid->z0_mm, grid->dx_mm, grid->dz_mm,
+                                     grid->fill, out, reinterpret_cast<hipStream_t>(stream)),
+            "scan conversion kernel launch");
+    return DUS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // plan: batched fused forward + MSE + adjoint, replayed from a HIP graph
 // ---------------------------------------------------------------------------

@@ -98,6 +98,13 @@ hipError_t launch_pose_finalize(const double *acc, const float *poses, int n_pos
                                 float *grad_pose, hipStream_t st);
 hipError_t launch_footprint(const VolArgs &v, const FanTable &t, const float *poses, uint8_t *mask,
                             hipStream_t st);
+// impedance at every ray sample (image layout)
+hipError_t launch_sample(int xcd_group, const VolArgs &v, const FanTable &t, const float *poses, float *out,
+                         hipStream_t st);
+// one fan's polar image onto an nz x nx grid of the probe's x-z plane
+hipError_t launch_scan_convert(const float *img, int n_rays, int n_samples, double aperture, double r0,
+                               double ds, int nx, int nz, double x0, double z0, double dx, double dz,
+                               float fill, float *out, hipStream_t st);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t st);

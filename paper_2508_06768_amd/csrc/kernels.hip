@@ -1539,6 +1539,61 @@ __global__ __launch_bounds__(64) void k_footprint(VolArgs v, FanTable tab, const
 }
 
 // --------------------------------------------------------------------------
+// sampling-only render: the impedance at every ray sample (one wavefront per
+// ray, coalesced stores)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_sample_rays(VolArgs v, FanTable tab, const float *__restrict__ poses,
+                                                   float *__restrict__ out, int xgrp)
+{
+    const int lane = threadIdx.x;
+    const int g = remap_block(blockIdx.x, gridDim.x, xgrp);
+    const int fi = find_fan(tab, g);
+    const FanRec fr = tab.f[fi];
+    const int j = g - fr.ray_begin;
+    const int S = fr.n_samples;
+    PhysArgs p{};
+    p.atten = 2;
+    Ray ray;
+    setup_ray(v, p, fr, poses, j, ray);
+    const long long obase = fr.out_offset + (long long)j * S;
+    const int sxy = v.nx * v.ny;
+#pragma unroll 4
+    for (int k = lane; k < S; k += 64) {
+        const Stencil st = stencil_at(v, ray, k);
+        out[obase + k] = (float)trilinear(v.Z, v.nx, sxy, st, nullptr);
+    }
+}
+
+// --------------------------------------------------------------------------
+// scan conversion of one fan's polar image onto a Cartesian grid of the
+// probe's x-z plane (one thread per output pixel, FP64 geometry)
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan_convert(const float *__restrict__ img, int n_r, int S, double A,
+                                                      double r0, double ds, int nx, int nz, double x0, double z0,
+                                                      double dx, double dz, float fill, float *__restrict__ out)
+{
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long long)nx * nz) return;
+    const int iz = (int)(idx / nx), ix = (int)(idx - (long long)iz * nx);
+    const double x = x0 + (double)ix * dx, z = z0 + (double)iz * dz;
+    const double r = sqrt(x * x + z * z);
+    const double th = atan2(x, z);
+    const double jr = (th + 0.5 * A) * (double)(n_r - 1) / A;
+    const double kr = (r - r0) / ds;
+    if (!(jr >= 0.0 && jr <= (double)(n_r - 1) && kr >= 0.0 && kr <= (double)(S - 1))) {
+        out[idx] = fill;
+        return;
+    }
+    const int j0 = min((int)floor(jr), n_r - 2), k0 = min((int)floor(kr), S - 2);
+    const double fj = jr - (double)j0, fk = kr - (double)k0;
+    const float *p0 = img + (long long)j0 * S + k0;
+    const float *p1 = p0 + S;
+    const double a = lerp((double)p0[0], (double)p0[1], fk);
+    const double b = lerp((double)p1[0], (double)p1[1], fk);
+    out[idx] = (float)lerp(a, b, fj);
+}
+
+// --------------------------------------------------------------------------
 // small utilities
 // --------------------------------------------------------------------------
 __global__ void k_zero_f64(double *p, long long n)
@@ -1787,6 +1842,25 @@ hipError_t launch_pose_finalize(const double *acc, const float *poses, int n_pos
     if (n_poses <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pose_finalize, dim3((n_poses + 63) / 64), dim3(64), 0, st, acc, poses,
                        n_poses, grad_pose);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(int xcd_group, const VolArgs &v, const FanTable &t, const float *poses, float *out,
+                         hipStream_t st)
+{
+    if (t.total_rays <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sample_rays, dim3(t.total_rays), dim3(64), 0, st, v, t, poses, out, xcd_group);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_convert(const float *img, int n_rays, int n_samples, double aperture, double r0,
+                               double ds, int nx, int nz, double x0, double z0, double dx, double dz,
+                               float fill, float *out, hipStream_t st)
+{
+    const long long n = (long long)nx * nz;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_convert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, img, n_rays,
+                       n_samples, aperture, r0, ds, nx, nz, x0, z0, dx, dz, fill, out);
     return hipGetLastError();
 }
 

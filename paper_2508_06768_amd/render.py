@@ -211,6 +211,29 @@ def get_schedule() -> dict:
             "scatter_rays": s.scatter_rays}
 
 
+def sample_volume(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, out: torch.Tensor | None = None):
+    """Sampling-only render: the impedance at every ray sample (packed image)."""
+    _check_inputs(Z, poses, geom)
+    if out is None:
+        out = torch.empty(max(geom.total, 1), dtype=torch.float32, device=Z.device)
+    check(_lib.lib().dus_sample_volume(_ptr(Z), ctypes.byref(geom.vol_c), _ptr(poses), geom.fans_c, geom.n_poses,
+                                       _ptr(out), _stream()), "dus_sample_volume")
+    return out[:geom.total]
+
+
+def scan_convert(bmode: torch.Tensor, geom: Geometry, pose: int, nx: int, nz: int, x0_mm: float, z0_mm: float,
+                 dx_mm: float, dz_mm: float, fill: float = 0.0) -> torch.Tensor:
+    """Pose `pose`'s polar image (inside the packed `bmode`) on an nz x nx
+    Cartesian grid of the probe's x-z plane."""
+    if not (bmode.is_cuda and bmode.dtype == torch.float32 and bmode.is_contiguous()):
+        raise ValueError("bmode must be a contiguous CUDA float32 tensor")
+    out = torch.empty((max(nz, 0), max(nx, 0)), dtype=torch.float32, device=bmode.device)
+    grid = _lib.DusGrid2d(int(nx), int(nz), float(x0_mm), float(z0_mm), float(dx_mm), float(dz_mm), float(fill))
+    check(_lib.lib().dus_scan_convert(_ptr(bmode), ctypes.byref(geom.fans_c[pose]), ctypes.byref(grid), _ptr(out),
+                                      _stream()), "dus_scan_convert")
+    return out
+
+
 def footprint_voxels(poses: torch.Tensor, geom: Geometry) -> int:
     """Number of distinct voxels in the union of all trilinear stencils."""
     nz, ny, nx = geom.shape

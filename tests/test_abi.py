@@ -37,14 +37,15 @@ def test_exports_every_declared_symbol():
 def test_record_layout_matches_header(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text('#include "diffus.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dus_volume), sizeof(dus_fan),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dus_volume), sizeof(dus_fan),'
                    ' sizeof(dus_physics), sizeof(dus_schedule), offsetof(dus_fan, out_offset),'
-                   ' offsetof(dus_physics, seed)); return 0;}\n')
+                   ' offsetof(dus_physics, seed), sizeof(dus_grid2d), offsetof(dus_grid2d, fill)); return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(DusVolume), ctypes.sizeof(DusFan), ctypes.sizeof(DusPhysics),
-            ctypes.sizeof(_lib.DusSchedule), DusFan.out_offset.offset, DusPhysics.seed.offset]
+            ctypes.sizeof(_lib.DusSchedule), DusFan.out_offset.offset, DusPhysics.seed.offset,
+            ctypes.sizeof(_lib.DusGrid2d), _lib.DusGrid2d.fill.offset]
     assert got == want
 
 

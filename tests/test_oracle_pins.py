@@ -475,3 +475,61 @@ def test_banded_and_transfer_render_agree_on_phantom():
         a = O.render(vol, c.poses[0], fan, ph)
         b = O.render(vol, c.poses[0], fan, ph, solver="banded")
         assert np.linalg.norm(a - b) <= 1e-11 * np.linalg.norm(b)
+
+
+# --------------------------------------------------------------------------
+# display and ablation modes
+# --------------------------------------------------------------------------
+def test_sample_image_reproduces_linear_volume():
+    """Trilinear sampling is exact on a volume linear in the voxel indices:
+    the sampling-only image equals that linear function at the sample
+    positions, computed here independently (SciPy's rotation)."""
+    from scipy.spatial.transform import Rotation
+    n = (20, 24, 28)                                 # nx, ny, nz
+    h = np.array([0.8, 1.0, 1.2])
+    o = np.array([-1.0, 0.5, 2.0])
+    c0, cx, cy, cz = 1.5, 0.013, -0.007, 0.021
+    iz, iy, ix = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    Z = c0 + cx * ix + cy * iy + cz * iz
+    vol = O.Volume(Z, tuple(h), tuple(o))
+    pose = np.array([7.0, 12.0, 5.0, 0.11, -0.07, 0.23])
+    fan = O.Fan(9, 40, 0.7, 0.45, 1.0)
+    img = O.sample_image(vol, pose, fan)
+    R = Rotation.from_rotvec(pose[3:]).as_matrix()
+    th = -fan.aperture / 2 + np.arange(fan.n_rays) * fan.aperture / (fan.n_rays - 1)
+    s = fan.r0 + np.arange(fan.n_samples) * fan.ds
+    d = np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], axis=1) @ R.T          # [rays, 3]
+    p = pose[:3][None, None, :] + s[None, :, None] * d[:, None, :]                  # [rays, S, 3]
+    u = (p - o) / h
+    assert np.all(u >= 0) and np.all(u <= np.array(n) - 1)                           # no clamping
+    ref = c0 + cx * u[..., 0] + cy * u[..., 1] + cz * u[..., 2]
+    np.testing.assert_allclose(img, ref, rtol=0, atol=1e-12)
+
+
+def _scan_case():
+    fan = O.Fan(33, 100, 1.0, 0.5, 2.0)
+    grid = dict(nx=40, nz=60, x0=-25.3, z0=-3.1, dx=1.27, dz=0.93)
+    return fan, grid
+
+
+def test_scan_convert_geometry_pins():
+    """Bilinear interpolation reproduces functions linear in (angle, depth):
+    the depth image converts to r = |(x, z)|, the angle image to
+    atan2(x, z), a constant to itself; pixels outside the fan take `fill`."""
+    fan, g = _scan_case()
+    th = -fan.aperture / 2 + np.arange(fan.n_rays) * fan.aperture / (fan.n_rays - 1)
+    depth = fan.r0 + np.arange(fan.n_samples) * fan.ds
+    x = g["x0"] + np.arange(g["nx"]) * g["dx"]
+    z = g["z0"] + np.arange(g["nz"]) * g["dz"]
+    X, Zz = np.meshgrid(x, z)
+    r = np.hypot(X, Zz)
+    a = np.arctan2(X, Zz)
+    inside = (r >= fan.r0) & (r <= depth[-1]) & (np.abs(a) <= fan.aperture / 2)
+    assert 100 < inside.sum() < inside.size
+    out_r = O.scan_convert(np.tile(depth, (fan.n_rays, 1)), fan, fill=-7.0, **g)
+    out_t = O.scan_convert(np.tile(th[:, None], (1, fan.n_samples)), fan, fill=-7.0, **g)
+    out_c = O.scan_convert(np.full((fan.n_rays, fan.n_samples), 3.25), fan, fill=-7.0, **g)
+    np.testing.assert_allclose(out_r[inside], r[inside], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out_t[inside], a[inside], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out_c[inside], 3.25, rtol=0, atol=1e-12)
+    assert np.all(out_r[~inside] == -7.0) and np.all(out_c[~inside] == -7.0)
