@@ -196,6 +196,30 @@ typedef struct {
 int dus_scan_convert(const float *bmode, const dus_fan *fan, const dus_grid2d *grid, float *out, void *stream);
 
 /*
+ * Volume reconstruction (the second use of the gradient that the paper names,
+ * Sec. 1 and Sec. 4: recovering Z from B-modes): a smoothness prior on Z,
+ *   R(Z) = weight * sum over the axes a, over the neighbour pairs
+ *          (v, v + e_a) inside the volume, of ((Z[v + e_a] - Z[v]) / h_a)^2,
+ * and an Adam update.  dus_smoothness adds dR/dZ to grad_Z (device FP32,
+ * +=) and R to *loss (device FP64 scalar or NULL, +=).  Workspace:
+ * dus_smoothness_workspace_bytes(vol) bytes (per-block energy partials),
+ * 256-byte aligned.
+ */
+int64_t dus_smoothness_workspace_bytes(const dus_volume *vol);
+int dus_smoothness(const float *Z, const dus_volume *vol, float weight, float *grad_Z, double *loss,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One Adam step (Kingma and Ba, ICLR 2015) on n FP32 parameters in place:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   x = clamp(x - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), lo, hi),
+ * t >= 1 the step count.  With lo > 0 it keeps an impedance volume positive
+ * (Eq. 1 needs Z > 0).  x, m, v are updated; grad is read.
+ */
+int dus_adam_step(float *x, const float *grad, float *m, float *v, int64_t n, float lr, float beta1,
+                  float beta2, float eps, int32_t t, float lo, float hi, void *stream);
+
+/*
  * Footprint of the rendering: mask[v] = 1 for every voxel v that is a corner
  * of the trilinear stencil of some sample of some ray (other entries are left
  * untouched).  mask: device uint8 [nz][ny][nx].  Used to count the distinct

@@ -248,6 +248,41 @@ def scan_convert(img, fan: Fan, nx: int, nz: int, x0: float, z0: float, dx: floa
     return out
 
 
+def smoothness(Z, spacing, weight: float):
+    """Smoothness prior of the reconstruction, written from its definition:
+    R = weight * sum over axes a of sum over neighbour pairs (v, v + e_a) of
+    ((Z[v + e_a] - Z[v]) / h_a)^2, with its gradient.  Z is [nz][ny][nx];
+    spacing = (h_x, h_y, h_z).  Returns (R, dR/dZ)."""
+    Z = np.asarray(Z, dtype=np.float64)
+    g = np.zeros_like(Z)
+    R = 0.0
+    for axis, h in ((2, spacing[0]), (1, spacing[1]), (0, spacing[2])):
+        w = weight / (h * h)
+        n = Z.shape[axis]
+        for i in range(n - 1):
+            a = [slice(None)] * 3
+            b = [slice(None)] * 3
+            a[axis] = i
+            b[axis] = i + 1
+            d = Z[tuple(b)] - Z[tuple(a)]
+            R += w * float(np.sum(d * d))
+            g[tuple(a)] -= 2.0 * w * d
+            g[tuple(b)] += 2.0 * w * d
+    return R, g
+
+
+def adam(x, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float, lo: float, hi: float):
+    """One Adam step (Kingma and Ba, 2015) with the result clamped to
+    [lo, hi]; returns (x, m, v) as new arrays (FP64)."""
+    x, g, m, v = (np.asarray(a, dtype=np.float64) for a in (x, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    x = np.clip(x - lr * mh / (np.sqrt(vh) + eps), lo, hi)
+    return x, m, v
+
+
 def sample(vol: Volume, u):
     L = lib()
     uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(3))

@@ -68,6 +68,11 @@ SIGNATURES = {
     "dus_sample_volume": (ctypes.c_int, [c_vp, ctypes.POINTER(DusVolume), c_vp, ctypes.POINTER(DusFan), c_i32,
                                          c_vp, c_vp]),
     "dus_scan_convert": (ctypes.c_int, [c_vp, ctypes.POINTER(DusFan), ctypes.POINTER(DusGrid2d), c_vp, c_vp]),
+    "dus_smoothness_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(DusVolume)]),
+    "dus_smoothness": (ctypes.c_int, [c_vp, ctypes.POINTER(DusVolume), ctypes.c_float, c_vp, c_vp, c_vp, c_sz,
+                                      c_vp]),
+    "dus_adam_step": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, c_i32, ctypes.c_float, ctypes.c_float, c_vp]),
     "dus_footprint_mask": (ctypes.c_int, [ctypes.POINTER(DusVolume), c_vp, ctypes.POINTER(DusFan), c_i32,
                                           c_vp, c_vp]),
     "dus_set_schedule": (ctypes.c_int, [ctypes.POINTER(DusSchedule)]),

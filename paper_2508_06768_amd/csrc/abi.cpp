@@ -518,6 +518,52 @@ int dus_scan_convert(const float *bmode, const dus_fan *fan, const dus_grid2d *g
     return DUS_OK;
 }
 
+int64_t dus_smoothness_workspace_bytes(const dus_volume *vol)
+{
+    if (check_volume(vol) != DUS_OK) return DUS_EINVAL;
+    return (int64_t)align_up((size_t)std::max<int64_t>(dus::smooth_blocks(vol->nx, vol->ny, vol->nz), 1) *
+                             sizeof(double));
+}
+
+int dus_smoothness(const float *Z, const dus_volume *vol, float weight, float *grad_Z, double *loss, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    int s;
+    if ((s = check_volume(vol)) != DUS_OK) return s;
+    if (!finite_f(weight) || weight < 0.0f) return fail(DUS_EINVAL, "weight must be finite and >= 0");
+    if (!Z || !grad_Z) return fail(DUS_EINVAL, "Z and grad_Z are required");
+    const int64_t need = dus_smoothness_workspace_bytes(vol);
+    if ((s = check_ws(ws, ws_bytes, (size_t)need)) != DUS_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float wx = weight / (vol->spacing_mm[0] * vol->spacing_mm[0]);
+    const float wy = weight / (vol->spacing_mm[1] * vol->spacing_mm[1]);
+    const float wz = weight / (vol->spacing_mm[2] * vol->spacing_mm[2]);
+    double *part = reinterpret_cast<double *>(ws);
+    DUS_HIP(dus::launch_smooth(Z, vol->nx, vol->ny, vol->nz, wx, wy, wz, grad_Z, part, st), "smoothness kernel launch");
+    if (loss)
+        DUS_HIP(dus::launch_sum_f64(part, dus::smooth_blocks(vol->nx, vol->ny, vol->nz), loss, st, true),
+                "smoothness sum kernel launch");
+    return DUS_OK;
+}
+
+int dus_adam_step(float *x, const float *grad, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+                  float eps, int32_t t, float lo, float hi, void *stream)
+{
+    if (n < 0) return fail(DUS_ESHAPE, "n < 0");
+    if (n == 0) return DUS_OK;
+    if (!x || !grad || !m || !v) return fail(DUS_EINVAL, "NULL pointer");
+    if (t < 1) return fail(DUS_EINVAL, "t must be >= 1");
+    if (!finite_f(lr) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !finite_f(eps) || eps < 0.0f || !(lo <= hi))
+        return fail(DUS_EINVAL, "bad Adam parameters");
+    const float c1 = (float)(1.0 - pow((double)beta1, (double)t));
+    const float c2 = (float)(1.0 - pow((double)beta2, (double)t));
+    DUS_HIP(dus::launch_adam(x, grad, m, v, n, lr, beta1, beta2, eps, c1, c2, lo, hi,
+                             reinterpret_cast<hipStream_t>(stream)),
+            "Adam kernel launch");
+    return DUS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // plan: batched fused forward + MSE + adjoint, replayed from a HIP graph
 // ---------------------------------------------------------------------------

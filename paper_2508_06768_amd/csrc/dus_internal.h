@@ -109,7 +109,15 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t st);
 // *out = sum of the n partials (the loss of the fused step)
-hipError_t launch_sum_f64(const double *part, int64_t n, double *out, hipStream_t st);
+hipError_t launch_sum_f64(const double *part, int64_t n, double *out, hipStream_t st, bool accumulate = false);
+// smoothness prior of the reconstruction: per-axis weights w / h^2; one
+// energy partial per block of 256 voxels (smooth_blocks of them)
+int64_t smooth_blocks(int nx, int ny, int nz);
+hipError_t launch_smooth(const float *Z, int nx, int ny, int nz, float wx, float wy, float wz, float *gZ,
+                         double *part, hipStream_t st);
+// Adam with bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t, result clamped to [lo, hi]
+hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, float lo, float hi, hipStream_t st);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t st);
 hipError_t launch_pixel_gain(const PhysArgs &p, const FanRec &f, float *out, hipStream_t st);

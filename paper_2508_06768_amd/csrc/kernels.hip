@@ -1067,7 +1067,8 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
 // scatter of dL/dZ_k: trilinear weights into the volume gradient.  One
 // wavefront takes RB neighbouring rays of one fan (64/RB lanes per ray) and
 // one segment of `seg` depths (blockIdx.y), and walks them together in
-// groups of 256/RB depths; every lane owns 4 consecutive depths of its ray.  A straight ray meets each cell once, so a
+// groups of 256/RB depths; every lane owns 4 consecutive depths of its ray.
+// A straight ray meets each cell once, so a
 // lane's consecutive samples in one cell form a run that it sums in
 // registers before touching memory.  The stencils of a group fill a small
 // box of the volume (neighbouring rays of a fan overlap); the runs go into an
@@ -1618,8 +1619,10 @@ __global__ void k_zero_f32(float *p, long long n)
     }
 }
 
-// out = sum of n partials (single block, fixed order: deterministic)
-__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, long long n, double *__restrict__ out)
+// out = sum of n partials, or out += it (single block, fixed order:
+// deterministic)
+__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, long long n, double *__restrict__ out,
+                                                 int accumulate)
 {
     __shared__ double s_w[4];
     double acc = 0.0;
@@ -1627,7 +1630,63 @@ __global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) *out = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+    if (threadIdx.x == 0) {
+        const double t = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+        *out = accumulate ? *out + t : t;
+    }
+}
+
+// --------------------------------------------------------------------------
+// volume reconstruction helpers: the smoothness prior
+//   R = w sum_axes sum_{pairs along the axis} ((Z_b - Z_a) / h_axis)^2
+// (one thread per voxel: grad_Z += dR/dZ of its own voxel, and the energy of
+// the pairs to its +x, +y, +z neighbours into a per-block partial), and the
+// element-wise Adam update with the result clamped to [lo, hi]
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_smooth(const float *__restrict__ Z, int nx, int ny, int nz, float wx,
+                                                float wy, float wz, float *__restrict__ gZ,
+                                                double *__restrict__ part)
+{
+    const long long n = (long long)nx * ny * nz;
+    const long long v = (long long)blockIdx.x * 256 + threadIdx.x;
+    double e = 0.0;
+    if (v < n) {
+        const int ix = (int)(v % nx);
+        const long long r = v / nx;
+        const int iy = (int)(r % ny), iz = (int)(r / ny);
+        const long long sxy = (long long)nx * ny;
+        const float z = Z[v];
+        float g = 0.0f;
+        // axis weights w / h^2; d(Z_b - Z_a)^2 / dZ = -2 (Z_b - Z_a) for a, +2 for b
+        if (ix > 0) g += 2.0f * wx * (z - Z[v - 1]);
+        if (ix + 1 < nx) { const float d = Z[v + 1] - z; g -= 2.0f * wx * d; e += (double)wx * (double)d * (double)d; }
+        if (iy > 0) g += 2.0f * wy * (z - Z[v - nx]);
+        if (iy + 1 < ny) { const float d = Z[v + nx] - z; g -= 2.0f * wy * d; e += (double)wy * (double)d * (double)d; }
+        if (iz > 0) g += 2.0f * wz * (z - Z[v - sxy]);
+        if (iz + 1 < nz) { const float d = Z[v + sxy] - z; g -= 2.0f * wz * d; e += (double)wz * (double)d * (double)d; }
+        gZ[v] += g;
+    }
+    __shared__ double s_w[4];
+    e = wave_sum(e);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ x, const float *__restrict__ g,
+                                              float *__restrict__ m, float *__restrict__ v, long long n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2, float lo, float hi)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        // bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t
+        const float step = lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        x[i] = fminf(fmaxf(x[i] - step, lo), hi);
+    }
 }
 
 __global__ void k_copy_f64(const double *s, double *d, long long n)
@@ -1887,9 +1946,29 @@ hipError_t launch_zero_f32(float *ptr, int64_t n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_sum_f64(const double *part, int64_t n, double *out, hipStream_t st)
+hipError_t launch_sum_f64(const double *part, int64_t n, double *out, hipStream_t st, bool accumulate)
 {
-    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, (long long)n, out);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, (long long)n, out, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+int64_t smooth_blocks(int nx, int ny, int nz) { return ((int64_t)nx * ny * nz + 255) / 256; }
+
+hipError_t launch_smooth(const float *Z, int nx, int ny, int nz, float wx, float wy, float wz, float *gZ,
+                         double *part, hipStream_t st)
+{
+    const int64_t blocks = smooth_blocks(nx, ny, nz);
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_smooth, dim3((unsigned)blocks), dim3(256), 0, st, Z, nx, ny, nz, wx, wy, wz, gZ, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, float lo, float hi, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n, 256)), dim3(256), 0, st, x, g, m, v, (long long)n, lr, b1, b2,
+                       eps, c1, c2, lo, hi);
     return hipGetLastError();
 }
 

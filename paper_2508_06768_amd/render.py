@@ -234,13 +234,43 @@ def scan_convert(bmode: torch.Tensor, geom: Geometry, pose: int, nx: int, nz: in
     return out
 
 
-def footprint_voxels(poses: torch.Tensor, geom: Geometry) -> int:
-    """Number of distinct voxels in the union of all trilinear stencils."""
+def smoothness(Z: torch.Tensor, geom: Geometry, weight: float, grad_Z: torch.Tensor,
+               loss: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> None:
+    """Smoothness prior: grad_Z += dR/dZ and loss += R (FP64 device scalar)."""
+    if not (Z.is_cuda and Z.dtype == torch.float32 and Z.is_contiguous() and tuple(Z.shape) == tuple(geom.shape)):
+        raise ValueError("Z must be a contiguous CUDA float32 tensor of the geometry's shape")
+    L = _lib.lib()
+    if ws is None:
+        nbytes = int(L.dus_smoothness_workspace_bytes(ctypes.byref(geom.vol_c)))
+        ws = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=Z.device)
+    check(L.dus_smoothness(_ptr(Z), ctypes.byref(geom.vol_c), float(weight), _ptr(grad_Z), _ptr(loss), _ptr(ws),
+                           ws.numel() * ws.element_size(), _stream()), "dus_smoothness")
+
+
+def adam_step(x: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, t: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, lo: float = -3.4e38,
+              hi: float = 3.4e38) -> None:
+    """One Adam step on x in place (m, v updated), x clamped to [lo, hi]."""
+    for a in (x, grad, m, v):
+        if not (a.is_cuda and a.dtype == torch.float32 and a.is_contiguous() and a.numel() == x.numel()):
+            raise ValueError("x, grad, m, v must be contiguous CUDA float32 tensors of one size")
+    check(_lib.lib().dus_adam_step(_ptr(x), _ptr(grad), _ptr(m), _ptr(v), x.numel(), float(lr), float(beta1),
+                                   float(beta2), float(eps), int(t), float(lo), float(hi), _stream()),
+          "dus_adam_step")
+
+
+def footprint_mask(poses: torch.Tensor, geom: Geometry) -> torch.Tensor:
+    """uint8 [nz][ny][nx]: 1 on every voxel of some trilinear stencil."""
     nz, ny, nx = geom.shape
-    mask = torch.zeros(nz * ny * nx, dtype=torch.uint8, device=poses.device)
+    mask = torch.zeros((nz, ny, nx), dtype=torch.uint8, device=poses.device)
     check(_lib.lib().dus_footprint_mask(ctypes.byref(geom.vol_c), _ptr(poses), geom.fans_c, geom.n_poses,
                                         _ptr(mask), _stream()), "dus_footprint_mask")
-    return int(mask.sum(dtype=torch.int64).item())
+    return mask
+
+
+def footprint_voxels(poses: torch.Tensor, geom: Geometry) -> int:
+    """Number of distinct voxels in the union of all trilinear stencils."""
+    return int(footprint_mask(poses, geom).sum(dtype=torch.int64).item())
 
 
 class FusedStep:

@@ -222,3 +222,42 @@ def test_scan_convert_matches_oracle():
         np.testing.assert_array_equal(out == -1.0, ref == -1.0)
         scale = np.abs(ref[ref != -1.0]).max()
         np.testing.assert_allclose(out, ref, rtol=0, atol=1e-6 * scale)
+
+
+# --------------------------------------------------------------------------
+# volume reconstruction helpers
+# --------------------------------------------------------------------------
+def test_smoothness_matches_oracle():
+    """Smoothness prior on a 37 x 23 x 19 volume (partial blocks), anisotropic
+    spacing: gradient added to an existing grad_Z, energy added to a loss."""
+    from oracle import oracle as O
+    from paper_2508_06768_amd.render import Geometry, smoothness
+    rng = np.random.default_rng(61)
+    Zn = (1.5 + 0.1 * rng.standard_normal((19, 23, 37))).astype(np.float32)
+    h = (0.8, 1.1, 1.3)
+    geom = Geometry(Zn.shape, h, (0.0, 0.0, 0.0), [], synth.PhysicsSpec())
+    Z = torch.from_numpy(Zn).to(DEV)
+    g0 = rng.standard_normal(Zn.shape).astype(np.float32)
+    gZ = torch.from_numpy(g0).to(DEV)
+    loss = torch.full((1,), 0.5, dtype=torch.float64, device=DEV)
+    smoothness(Z, geom, 0.37, gZ, loss)
+    R, g = O.smoothness(Zn.astype(np.float64), tuple(float(np.float32(x)) for x in h), float(np.float32(0.37)))
+    assert loss.item() - 0.5 == pytest.approx(R, rel=1e-6)
+    np.testing.assert_allclose(gZ.cpu().numpy() - g0, g, rtol=0, atol=1e-5 * np.abs(g).max())
+
+
+def test_adam_matches_oracle():
+    from oracle import oracle as O
+    from paper_2508_06768_amd.render import adam_step
+    rng = np.random.default_rng(62)
+    n = 100003
+    x0, g, m0 = (rng.standard_normal(n).astype(np.float32) for _ in range(3))
+    v0 = np.abs(rng.standard_normal(n)).astype(np.float32)
+    x, gg, m, v = (torch.from_numpy(a.copy()).to(DEV) for a in (x0, g, m0, v0))
+    hyper = (0.01, 0.9, 0.999, 1e-8, -1.5, 2.5)
+    adam_step(x, gg, m, v, 7, *hyper)
+    # the hyperparameters travel as FP32: the oracle takes the same values
+    rx, rm, rv = O.adam(x0, g, m0, v0, 7, *(float(np.float32(a)) for a in hyper))
+    np.testing.assert_allclose(m.cpu().numpy(), rm, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(v.cpu().numpy(), rv, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(x.cpu().numpy(), rx, rtol=1e-6, atol=1e-6)

@@ -533,3 +533,40 @@ def test_scan_convert_geometry_pins():
     np.testing.assert_allclose(out_t[inside], a[inside], rtol=0, atol=1e-12)
     np.testing.assert_allclose(out_c[inside], 3.25, rtol=0, atol=1e-12)
     assert np.all(out_r[~inside] == -7.0) and np.all(out_c[~inside] == -7.0)
+
+
+# --------------------------------------------------------------------------
+# volume reconstruction helpers
+# --------------------------------------------------------------------------
+def test_smoothness_closed_form_and_differences():
+    """A volume linear along x has R = w (a/h_x)^2 (nx-1) ny nz and a zero
+    gradient inside; the gradient of a random volume matches central
+    differences of R."""
+    nx, ny, nz, a = 7, 5, 4, 0.25          # dyadic slope: every difference exact
+    h = (0.8, 1.1, 1.3)
+    Z = np.broadcast_to(a * np.arange(nx, dtype=np.float64), (nz, ny, nx)).copy()
+    R, g = O.smoothness(Z, h, 0.7)
+    assert R == pytest.approx(0.7 * (a / h[0]) ** 2 * (nx - 1) * ny * nz, rel=1e-13)
+    assert np.all(g[:, :, 1:-1] == 0.0)
+    assert np.all(g[:, :, 0] < 0) and np.all(g[:, :, -1] > 0)
+    rng = np.random.default_rng(3)
+    Zr = rng.standard_normal((nz, ny, nx))
+    _, gr = O.smoothness(Zr, h, 0.7)
+    eps = 1e-6
+    for idx in [(0, 0, 0), (1, 2, 3), (3, 4, 6), (2, 0, 5)]:
+        zp = Zr.copy(); zp[idx] += eps
+        zm = Zr.copy(); zm[idx] -= eps
+        fd = (O.smoothness(zp, h, 0.7)[0] - O.smoothness(zm, h, 0.7)[0]) / (2 * eps)
+        assert fd == pytest.approx(gr[idx], rel=1e-7, abs=1e-9)
+
+
+def test_adam_first_step_closed_form():
+    """At t = 1 the bias-corrected moments are g and g^2, so the step is
+    lr g / (|g| + eps); the result is clamped."""
+    g = np.array([2.0, -0.5, 1e-3, 0.0])
+    x0 = np.array([1.0, 1.0, 1.0, 1.0])
+    x, m, v = O.adam(x0, g, np.zeros(4), np.zeros(4), 1, 0.1, 0.9, 0.999, 1e-8, 0.95, 2.0)
+    want = np.clip(x0 - 0.1 * g / (np.abs(g) + 1e-8), 0.95, 2.0)
+    np.testing.assert_allclose(x, want, rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
