@@ -315,18 +315,19 @@ __device__ __forceinline__ float rayleigh(uint32_t x)
     return __builtin_amdgcn_sqrtf(-0.88254240061060638f * __builtin_amdgcn_logf(u));
 }
 
-// Speckle inputs of one tile [t0, t0+T): granular variates per pixel and the
-// radial cell values covering the tile.
-template <int T>
-__device__ __forceinline__ void speckle_fill(const PhysArgs &p, int t0, int j, int sid, int lane,
-                                             float *s_xig, float *s_xir)
+// granular variates of samples 4 ctr .. 4 ctr + 3 of ray j
+__device__ __forceinline__ void granular4(const PhysArgs &p, int ctr, int j, int sid, float x[4])
 {
-    for (int bb = lane; bb < T / 4; bb += 64) {
-        uint32_t w[4];
-        philox((uint32_t)((t0 >> 2) + bb), (uint32_t)j, (uint32_t)sid, 0u, p.key0, p.key1, w);
-        float4 x = make_float4(rayleigh(w[0]), rayleigh(w[1]), rayleigh(w[2]), rayleigh(w[3]));
-        *reinterpret_cast<float4 *>(s_xig + 4 * bb) = x;
-    }
+    uint32_t w[4];
+    philox((uint32_t)ctr, (uint32_t)j, (uint32_t)sid, 0u, p.key0, p.key1, w);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = rayleigh(w[q]);
+}
+
+// radial cell values covering the tile [t0, t0+T): s_xir[c - t0/cell]
+template <int T>
+__device__ __forceinline__ void speckle_radial(const PhysArgs &p, int t0, int j, int sid, int lane, float *s_xir)
+{
     const int cell = p.cell;
     const int c_lo = t0 / cell, c_hi = (t0 + T - 1) / cell + 1;
     for (int b = (c_lo >> 2) + lane; b <= (c_hi >> 2); b += 64) {
@@ -340,6 +341,20 @@ __device__ __forceinline__ void speckle_fill(const PhysArgs &p, int t0, int j, i
     }
 }
 
+// Speckle inputs of one tile [t0, t0+T): granular variates per pixel and the
+// radial cell values covering the tile.
+template <int T>
+__device__ __forceinline__ void speckle_fill(const PhysArgs &p, int t0, int j, int sid, int lane,
+                                             float *s_xig, float *s_xir)
+{
+    for (int bb = lane; bb < T / 4; bb += 64) {
+        float x[4];
+        granular4(p, (t0 >> 2) + bb, j, sid, x);
+        *reinterpret_cast<float4 *>(s_xig + 4 * bb) = make_float4(x[0], x[1], x[2], x[3]);
+    }
+    speckle_radial<T>(p, t0, j, sid, lane, s_xir);
+}
+
 // per-launch constants of pixel_gain: 1/(S-1) and 1/cell
 struct GainK {
     float inv_sm1, inv_cell;
@@ -350,15 +365,16 @@ __device__ __forceinline__ GainK gain_consts(const PhysArgs &p, int S)
     return GainK{S > 1 ? 1.0f / (float)(S - 1) : 0.0f, 1.0f / (float)p.cell};
 }
 
-// Gain of pixel k (tile index i): post-hoc attenuation times speckle.
-// zeta = k/(S-1) and the cell fraction come from reciprocals (within an ulp
-// of the quotients); the cell index is exact.
-template <bool SPK>
-__device__ __forceinline__ float pixel_gain(const PhysArgs &p, const GainK &gk, int k, int i, int t0,
-                                            float postc, const float *s_xig, const float *s_xir)
+// Gain of pixel k: post-hoc attenuation (POST) times speckle (SPK), with xg
+// the pixel's granular variate and s_xir the radial cell values of the tile
+// starting at t0.  zeta = k/(S-1) and the cell fraction come from reciprocals
+// (within an ulp of the quotients); the cell index is exact.
+template <bool SPK, bool POST>
+__device__ __forceinline__ float pixel_gain(const PhysArgs &p, const GainK &gk, int k, int t0, float postc,
+                                            float xg, const float *s_xir)
 {
     float g = 1.0f;
-    if (p.atten == 1) g = exp2f((float)((double)k * (double)postc));
+    if (POST) g = exp2f((float)((double)k * (double)postc));
     if (SPK) {
         const float zeta = (float)k * gk.inv_sm1;
         const int cell = p.cell;
@@ -369,7 +385,6 @@ __device__ __forceinline__ float pixel_gain(const PhysArgs &p, const GainK &gk, 
         const float fr = (float)r * gk.inv_cell;
         const int c_lo = t0 / cell;
         const float xr = (1.0f - fr) * s_xir[c - c_lo] + fr * s_xir[c + 1 - c_lo];
-        const float xg = s_xig[i];
         // zeta^gam with zeta in [1/(S-1), 1] (a normal number); a power below
         // 2^-126 may flush to zero, which leaves the FP32 gain unchanged
         float pw;
@@ -378,6 +393,15 @@ __device__ __forceinline__ float pixel_gain(const PhysArgs &p, const GainK &gk, 
         g *= 1.0f + p.Ar * pw * (xr - 1.0f) + (p.Ag0 + p.Ag1 * zeta) * (xg - 1.0f);
     }
     return g;
+}
+
+// the same with the post-hoc switch read at run time
+template <bool SPK>
+__device__ __forceinline__ float pixel_gain_rt(const PhysArgs &p, const GainK &gk, int k, int t0, float postc,
+                                               float xg, const float *s_xir)
+{
+    return (p.atten == 1) ? pixel_gain<SPK, true>(p, gk, k, t0, postc, xg, s_xir)
+                          : pixel_gain<SPK, false>(p, gk, k, t0, postc, xg, s_xir);
 }
 
 __device__ __forceinline__ float posthoc_coef(const PhysArgs &p, float ds)
@@ -548,8 +572,6 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     constexpr int LB = kCarryBlock / C;     // lanes per carry block
     __shared__ double s_rho[T + T / 16];
     __shared__ double s_zc[NB];
-    __shared__ float s_pix[T + T / 32];
-    __shared__ float s_xig[SPK ? T : 1];
     __shared__ float s_xir[SPK ? T / 4 + 8 : 1];
 
     const int lane = threadIdx.x;
@@ -577,7 +599,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
         const double zstart = zprev;
         gather_tile<C, false>(v, ray, t0, S, absm, lane, zprev, s_rho, nullptr, nullptr,
                               carry ? s_zc : nullptr);
-        if (SPK) speckle_fill<T>(p, t0, j, fr.speckle_id, lane, s_xig, s_xir);
+        if (SPK) speckle_radial<T>(p, t0, j, fr.speckle_id, lane, s_xir);
         __syncthreads();
 
         const int base = lane * C;
@@ -611,6 +633,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
         double v0 = fma(c0, X.a, c1 * X.c);
         double v1 = fma(c0, X.b, c1 * X.d);
         double D = cD * xd;
+        float pix[C];
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             // branch-free: outside [1, S) rho = 0 and the map is the identity,
@@ -620,13 +643,12 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             const double r = s_rho[pad8(base + i)];
             const Map m = make_map(r, a2, sgn, valid);
             const double v1n = fma(v0, r, v1);
-            const float pix = (float)(r * D * rcp64(v1 * v1n));
+            pix[i] = (float)(r * D * rcp64(v1 * v1n));
             if (want_piv) piv = valid ? fmin(piv, fabs(v1n * rcp64(v1))) : piv;
             const double v0n = fma(v0, m.m00, v1 * m.m10);
             v0 = v0n;
             v1 = v1n;
             D *= m.det;
-            s_pix[pad4(base + i)] = pix;
         }
         // carry to the next tile, renormalised by a power of two
         {
@@ -639,19 +661,49 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             cD = ldexp(nD, -2 * ex);
             first_rel = ex - e_last;
         }
-        __syncthreads();
-#pragma unroll 1
-        for (int m = 0; m < C; ++m) {
-            const int i = m * 64 + lane;
-            const int k = t0 + i;
-            if (k < S) {
-                float pix = s_pix[pad4(i)];
-                if (SPK || p.atten == 1) {
-                    const float gn = pixel_gain<SPK>(p, gk, k, i, t0, postc, s_xig, s_xir);
-                    pix *= gn;
-                    if (gain_out) gain_out[obase + k] = gn;
+        // per-pixel gains and the stores, in the lane's chunk order (the
+        // lane's C samples start at a multiple of 4: its granular variates
+        // are C/4 whole Philox blocks)
+        float gn[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) gn[i] = 1.0f;
+        if (SPK) {
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q) {
+                float x[4];
+                granular4(p, ((t0 + base) >> 2) + q, j, fr.speckle_id, x);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) gn[4 * q + u] = x[u];
+            }
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                gn[i] = (p.atten == 1) ? pixel_gain<true, true>(p, gk, t0 + base + i, t0, postc, gn[i], s_xir)
+                                       : pixel_gain<true, false>(p, gk, t0 + base + i, t0, postc, gn[i], s_xir);
+        } else if (p.atten == 1) {
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                gn[i] = pixel_gain<false, true>(p, gk, t0 + base + i, t0, postc, 1.0f, s_xir);
+        }
+        const bool has_gain = SPK || p.atten == 1;
+        const long long o = obase + t0 + base;
+        const bool vec = ((reinterpret_cast<uintptr_t>(out + o) & 15) == 0) &&
+                         (!gain_out || (reinterpret_cast<uintptr_t>(gain_out + o) & 15) == 0);
+        if (vec && t0 + base + C <= S) {
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q) {
+                const int i = 4 * q;
+                *reinterpret_cast<float4 *>(out + o + i) =
+                    make_float4(pix[i] * gn[i], pix[i + 1] * gn[i + 1], pix[i + 2] * gn[i + 2], pix[i + 3] * gn[i + 3]);
+                if (has_gain && gain_out)
+                    *reinterpret_cast<float4 *>(gain_out + o + i) = make_float4(gn[i], gn[i + 1], gn[i + 2], gn[i + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                if (t0 + base + i < S) {
+                    out[o + i] = pix[i] * gn[i];
+                    if (has_gain && gain_out) gain_out[o + i] = gn[i];
                 }
-                out[obase + k] = pix;
             }
         }
         __syncthreads();
@@ -843,7 +895,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             for (int m = 0; m < C; ++m) {
                 const int i = m * 64 + lane;
                 const int k = t0 + i;
-                const float gain = (has_gain && k < S) ? pixel_gain<SPK>(p, gk, k, i, t0, postc, s_xig, s_xir) : 1.0f;
+                const float gain = (has_gain && k < S) ? pixel_gain_rt<SPK>(p, gk, k, t0, postc, SPK ? s_xig[i] : 1.0f, s_xir) : 1.0f;
                 if (FUSED) s_gain[pad4(i)] = gain;
                 else s_eb[pad4(i)] *= gain;
             }
@@ -1723,7 +1775,7 @@ __global__ __launch_bounds__(64) void k_gain(PhysArgs p, FanRec fr, float *__res
     for (int m = 0; m < T / 64; ++m) {
         const int i = m * 64 + lane;
         const int k = t0 + i;
-        if (k < S) out[(long long)j * S + k] = pixel_gain<SPK>(p, gk, k, i, t0, postc, s_xig, s_xir);
+        if (k < S) out[(long long)j * S + k] = pixel_gain_rt<SPK>(p, gk, k, t0, postc, SPK ? s_xig[i] : 1.0f, s_xir);
     }
 }
 
