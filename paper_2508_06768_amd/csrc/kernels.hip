@@ -1128,44 +1128,17 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
 // global atomic per touched voxel, consecutive lanes on consecutive x.  A
 // group whose box does not fit falls back to per-sample global atomics.
 //
-// The box holds 64-bit fixed point: integer LDS atomics run at the rate of
-// plain LDS stores on gfx950, FP32 LDS atomics several times slower.  A
-// group's scale 2^F follows from the largest exponent of its dL/dZ values so
-// that the sum of all its contributions stays below 2^62: every contribution
-// within 2^38 of the group's largest is kept more finely than an FP32 add
-// would keep it.
+// The box holds FP64: FP64 LDS atomics (ds_add_f64) run at the rate of
+// plain LDS stores on gfx950, FP32 LDS atomics several times slower.  The
+// FP64 sum of a voxel's FP32 contributions is rounded to FP32 once, when the
+// box is flushed.
 // --------------------------------------------------------------------------
 constexpr int kScatterSpl = 4;     // consecutive depths per lane
 
 template <int RB>
 struct ScatterBox {
-    static constexpr int cap = RB == 2 ? 4096 : (RB == 4 ? 2048 : 1024);   // 64-bit entries
+    static constexpr int cap = RB == 2 ? 4096 : (RB == 4 ? 2048 : 1024);   // FP64 entries
 };
-
-// x 2^F rounded to the nearest integer; requires |x| 2^F < 2^62.  All in
-// FP32 and exact: y = rint(|x| 2^F) is an integer with at most 24
-// significant bits, hi = floor(y 2^-32), and lo = y - hi 2^32 in [0, 2^32)
-// keeps only bits of y (no rounding); the magnitude is hi 2^32 + lo.
-__device__ __forceinline__ long long to_fixed(float x, int F)
-{
-    const float y = __builtin_rintf(ldexpf(fabsf(x), F));
-    const float hi = floorf(y * 0x1p-32f);
-    const float lo = fmaf(-hi, 0x1p32f, y);
-    const long long mag = (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
-    return (x < 0.0f) ? -mag : mag;
-}
-
-// largest biased FP32 exponent over the wavefront (bitwise, by ballots)
-__device__ __forceinline__ int wave_max_exp(int e)
-{
-    int m = 0;
-#pragma unroll
-    for (int b = 7; b >= 0; --b) {
-        const int c = m | (1 << b);
-        if (__ballot(e >= c) != 0ull) m = c;
-    }
-    return m;
-}
 
 template <int RB>
 __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const float *__restrict__ poses,
@@ -1177,7 +1150,7 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
     constexpr int CAP = ScatterBox<RB>::cap;
     // s_box is all zeros between groups: cleared once here, and every flush
     // clears the entries it reads
-    __shared__ unsigned long long s_box[CAP];
+    __shared__ double s_box[CAP];
     const int lane = threadIdx.x;
     const int slot = lane / LPR, ll = lane % LPR;
     // depth chunk of this lane, rotated by the ray slot: in one instruction
@@ -1206,7 +1179,7 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
     setup_ray(v, p, fr, poses, ray_ok ? j : 0, ray, false);     // RB rays per wavefront
     const float *zrow = zbar + fr.out_offset + (long long)(ray_ok ? j : 0) * S;
     const int sxy = v.nx * v.ny;
-    for (int t = lane; t < CAP; t += 64) s_box[t] = 0ull;
+    for (int t = lane; t < CAP; t += 64) s_box[t] = 0.0;
     // dL/dZ of the next group is loaded one group ahead
     float zn[kScatterSpl];
 #pragma unroll
@@ -1285,12 +1258,6 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
             }
             continue;
         }
-        // fixed-point scale of the group: |dL/dZ| < 2^(emax - 126), at most
-        // 256 samples, weights summing to one per sample
-        int el = 0;
-#pragma unroll
-        for (int q = 0; q < kScatterSpl; ++q) el = max(el, (int)((__float_as_uint(zb[q]) >> 23) & 0xffu));
-        const int F = 180 - wave_max_exp(el);
         // runs of a lane summed in registers, one LDS atomic per corner and run
         {
             const int off[8] = {0, 1, rs, rs + 1, ps, ps + 1, ps + rs, ps + rs + 1};
@@ -1304,7 +1271,7 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
                         if (ra[c] != 0.0f)
-                            atomicAdd(&s_box[cur + off[c]], (unsigned long long)to_fixed(ra[c], F));
+                            atomicAdd(&s_box[cur + off[c]], (double)ra[c]);
                         ra[c] = 0.0f;
                     }
                 }
@@ -1324,7 +1291,7 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
                     if (ra[c] != 0.0f)
-                        atomicAdd(&s_box[cur + off[c]], (unsigned long long)to_fixed(ra[c], F));
+                        atomicAdd(&s_box[cur + off[c]], (double)ra[c]);
             }
         }
         __syncthreads();
@@ -1338,11 +1305,11 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
             const int dy = dyz % by, dz = dyz / by;
             int x = lane % bx, y = (lane / bx) % by, z = lane / (bx * by);
             for (int e0 = 0; e0 < E; e0 += 256) {
-                unsigned long long val[4];
+                double val[4];
                 int at[4], gi[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    val[u] = 0ull;
+                    val[u] = 0.0;
                     at[u] = gi[u] = 0;
                     if (e0 + 64 * u + lane < E) {
                         at[u] = z * ps + y * rs + x;
@@ -1357,9 +1324,9 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    if (val[u] != 0ull) {
-                        s_box[at[u]] = 0ull;
-                        const float xv = (float)ldexp((double)(long long)val[u], -F);
+                    if (val[u] != 0.0) {
+                        s_box[at[u]] = 0.0;
+                        const float xv = (float)val[u];
                         if (xv != 0.0f) atomicAdd(gZ + gi[u], xv);
                     }
                 }
