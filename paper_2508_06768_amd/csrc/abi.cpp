@@ -520,7 +520,8 @@ int dus_scan_convert(const float *bmode, const dus_fan *fan, const dus_grid2d *g
 
 int64_t dus_smoothness_workspace_bytes(const dus_volume *vol)
 {
-    if (check_volume(vol) != DUS_OK) return DUS_EINVAL;
+    int s;
+    if ((s = check_volume(vol)) != DUS_OK) return s;
     return (int64_t)align_up((size_t)std::max<int64_t>(dus::smooth_blocks(vol->nx, vol->ny, vol->nz), 1) *
                              sizeof(double));
 }

@@ -116,6 +116,20 @@ def _check_inputs(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry):
         raise ValueError("poses must be a contiguous float32 CUDA tensor [n_poses, 6]")
 
 
+def _check_buffer(t, name: str, numel: int, dtype=torch.float32, device=None):
+    """A buffer the library writes or reads through a raw pointer: it must be
+    a contiguous CUDA tensor of `dtype` with at least `numel` elements (the
+    C ABI cannot see sizes)."""
+    if t is None:
+        return
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+
+
 def render(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, want_pivot: bool = False,
            out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
     """Forward render; returns the packed image (and per-ray min pivots)."""
@@ -123,9 +137,11 @@ def render(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, want_pivot: boo
     dev = Z.device
     if out is None:
         out = torch.empty(max(geom.total, 1), dtype=torch.float32, device=dev)
+    _check_buffer(out, "out", geom.total, device=dev)
     piv = torch.empty(max(geom.total_rays, 1), dtype=torch.float32, device=dev) if want_pivot else None
     if ws is None:
         ws = geom.workspace(False, dev)
+    _check_buffer(ws, "ws", 0, torch.uint8, dev)
     check(_lib.lib().dus_render_bmode(_ptr(Z), ctypes.byref(geom.vol_c), _ptr(poses), geom.fans_c,
                                       geom.n_poses, ctypes.byref(geom.phys_c), _ptr(out), _ptr(piv),
                                       _ptr(ws), ws.numel(), _stream()),
@@ -141,14 +157,15 @@ def render_backward(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, grad_b
     _check_inputs(Z, poses, geom)
     dev = Z.device
     g = grad_bmode.contiguous().to(torch.float32)
-    if g.numel() < geom.total:
-        raise ValueError("grad_bmode too small")
+    _check_buffer(g, "grad_bmode", geom.total, device=dev)
     gZ = None
     if want_Z:
         gZ = grad_Z if grad_Z is not None else torch.zeros_like(Z)
+        _check_buffer(gZ, "grad_Z", Z.numel(), device=dev)
     gp = torch.empty((geom.n_poses, 6), dtype=torch.float32, device=dev) if want_pose else None
     if ws is None:
         ws = geom.workspace(True, dev)
+    _check_buffer(ws, "ws", 0, torch.uint8, dev)
     check(_lib.lib().dus_render_bmode_backward(_ptr(Z), ctypes.byref(geom.vol_c), _ptr(poses),
                                                geom.fans_c, geom.n_poses, ctypes.byref(geom.phys_c),
                                                _ptr(g), _ptr(gZ), _ptr(gp), _ptr(ws), ws.numel(),
@@ -216,6 +233,7 @@ def sample_volume(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, out: tor
     _check_inputs(Z, poses, geom)
     if out is None:
         out = torch.empty(max(geom.total, 1), dtype=torch.float32, device=Z.device)
+    _check_buffer(out, "out", geom.total, device=Z.device)
     check(_lib.lib().dus_sample_volume(_ptr(Z), ctypes.byref(geom.vol_c), _ptr(poses), geom.fans_c, geom.n_poses,
                                        _ptr(out), _stream()), "dus_sample_volume")
     return out[:geom.total]
@@ -225,8 +243,9 @@ def scan_convert(bmode: torch.Tensor, geom: Geometry, pose: int, nx: int, nz: in
                  dx_mm: float, dz_mm: float, fill: float = 0.0) -> torch.Tensor:
     """Pose `pose`'s polar image (inside the packed `bmode`) on an nz x nx
     Cartesian grid of the probe's x-z plane."""
-    if not (bmode.is_cuda and bmode.dtype == torch.float32 and bmode.is_contiguous()):
-        raise ValueError("bmode must be a contiguous CUDA float32 tensor")
+    if not 0 <= pose < geom.n_poses:
+        raise ValueError(f"pose {pose} out of range")
+    _check_buffer(bmode, "bmode", int(geom.offsets[pose + 1]))
     out = torch.empty((max(nz, 0), max(nx, 0)), dtype=torch.float32, device=bmode.device)
     grid = _lib.DusGrid2d(int(nx), int(nz), float(x0_mm), float(z0_mm), float(dx_mm), float(dz_mm), float(fill))
     check(_lib.lib().dus_scan_convert(_ptr(bmode), ctypes.byref(geom.fans_c[pose]), ctypes.byref(grid), _ptr(out),
@@ -239,9 +258,12 @@ def smoothness(Z: torch.Tensor, geom: Geometry, weight: float, grad_Z: torch.Ten
     """Smoothness prior: grad_Z += dR/dZ and loss += R (FP64 device scalar)."""
     if not (Z.is_cuda and Z.dtype == torch.float32 and Z.is_contiguous() and tuple(Z.shape) == tuple(geom.shape)):
         raise ValueError("Z must be a contiguous CUDA float32 tensor of the geometry's shape")
+    _check_buffer(grad_Z, "grad_Z", Z.numel(), device=Z.device)
+    _check_buffer(loss, "loss", 1, torch.float64, Z.device)
     L = _lib.lib()
     if ws is None:
-        nbytes = int(L.dus_smoothness_workspace_bytes(ctypes.byref(geom.vol_c)))
+        nbytes = int(check(L.dus_smoothness_workspace_bytes(ctypes.byref(geom.vol_c)),
+                           "dus_smoothness_workspace_bytes"))
         ws = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=Z.device)
     check(L.dus_smoothness(_ptr(Z), ctypes.byref(geom.vol_c), float(weight), _ptr(grad_Z), _ptr(loss), _ptr(ws),
                            ws.numel() * ws.element_size(), _stream()), "dus_smoothness")
@@ -307,8 +329,19 @@ class FusedStep:
             self._ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device=device)
         return self._ws
 
-    def step(self, Z, poses, target, bmode=None, loss=None, grad_Z=None, grad_pose=None):
+    def _check_step(self, Z, poses, target, bmode, loss, grad_Z, grad_pose):
         _check_inputs(Z, poses, self.geom)
+        dev = Z.device
+        if target is None:
+            raise ValueError("target is required")
+        _check_buffer(target, "target", self.geom.total, device=dev)
+        _check_buffer(bmode, "bmode", self.geom.total, device=dev)
+        _check_buffer(loss, "loss", 1, torch.float64, dev)
+        _check_buffer(grad_Z, "grad_Z", Z.numel(), device=dev)
+        _check_buffer(grad_pose, "grad_pose", 6 * self.geom.n_poses, device=dev)
+
+    def step(self, Z, poses, target, bmode=None, loss=None, grad_Z=None, grad_pose=None):
+        self._check_step(Z, poses, target, bmode, loss, grad_Z, grad_pose)
         ws = self.workspace(Z.device)
         check(_lib.lib().dus_plan_step(self._h, _ptr(Z), _ptr(poses), _ptr(target), _ptr(bmode), _ptr(loss),
                                        _ptr(grad_Z), _ptr(grad_pose), _ptr(ws), ws.numel(), _stream()),
@@ -317,7 +350,7 @@ class FusedStep:
     def step_timed(self, Z, poses, target, bmode=None, loss=None, grad_Z=None, grad_pose=None) -> dict:
         """One step launched eagerly with HIP events at the phase boundaries;
         returns {phase: ms} (blocks until the step has finished)."""
-        _check_inputs(Z, poses, self.geom)
+        self._check_step(Z, poses, target, bmode, loss, grad_Z, grad_pose)
         ws = self.workspace(Z.device)
         ms = (ctypes.c_float * len(_lib.PHASES))()
         check(_lib.lib().dus_plan_step_timed(self._h, _ptr(Z), _ptr(poses), _ptr(target), _ptr(bmode), _ptr(loss),

@@ -195,3 +195,13 @@ def test_schedule_validation():
         assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays) == (16, 8, 64, 2)
     finally:
         L.dus_set_schedule(ctypes.byref(old))
+
+
+def test_binding_refuses_host_buffers():
+    """Buffers handed to the library as raw device pointers must be CUDA
+    tensors; the binding checks before any call."""
+    import torch
+    from paper_2508_06768_amd.render import _check_buffer
+    with pytest.raises(ValueError, match="CUDA"):
+        _check_buffer(torch.zeros(4), "target", 4)
+    _check_buffer(None, "bmode", 4)      # optional buffers may be absent

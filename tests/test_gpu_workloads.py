@@ -174,6 +174,33 @@ def test_graph_replays_agree():
         assert H.rel_l2(r[3], ref[3]) <= 1e-6
 
 
+def test_binding_rejects_short_buffers():
+    """The raw-pointer ABI cannot see sizes: the binding refuses buffers
+    smaller than the geometry before anything is launched."""
+    from paper_2508_06768_amd.render import FusedStep, render, render_backward
+    from tests.test_gpu_parity import ragged_case
+    case = ragged_case(0, 0, False, seed=43)
+    geom, Z, P = _gpu(case)
+    step = FusedStep(geom, zero_grad_z=True)
+    T = torch.zeros(geom.total, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    gZ = torch.zeros_like(Z)
+    gp = torch.zeros((geom.n_poses, 6), device=DEV)
+    with pytest.raises(ValueError, match="target"):
+        step.step(Z, P, T[:-1], loss=loss, grad_Z=gZ, grad_pose=gp)
+    with pytest.raises(ValueError, match="grad_Z"):
+        step.step(Z, P, T, loss=loss, grad_Z=gZ.view(-1)[:-1], grad_pose=gp)
+    with pytest.raises(ValueError, match="grad_pose"):
+        step.step(Z, P, T, loss=loss, grad_Z=gZ, grad_pose=gp[:-1])
+    with pytest.raises(ValueError, match="loss"):
+        step.step(Z, P, T, loss=loss.float(), grad_Z=gZ, grad_pose=gp)
+    with pytest.raises(ValueError, match="out"):
+        render(Z, P, geom, out=torch.empty(geom.total - 1, device=DEV))
+    with pytest.raises(ValueError, match="grad_bmode"):
+        render_backward(Z, P, geom, T[:-1])
+    step.close()
+
+
 def test_edge_sizes():
     """Maximum samples per ray, single ray, one and two samples, an empty fan,
     and a volume with 2-voxel axes."""
