@@ -6,6 +6,9 @@
   parameters) within 1e-3;
 * the uneven 64-pose batch: batched launch == one pose per launch, and
   sampled poses against the oracle;
+* the benchmark's own fused step (64 x 256 x 1024, effects on, graph
+  replay, default and tuned schedules): all images, the loss, dL/dZ and all
+  pose gradients against the oracle;
 * every schedule gives the same result; graph replays agree;
 * maximum sample count, single ray, single sample, empty fans, 2-voxel axes.
 """
@@ -118,6 +121,54 @@ def test_batched_equals_plain_and_oracle():
         rep = H.parity_report(img[o[p]:o[p + 1]], ref)
         print("pose", p, case.fans[p], rep, flush=True)
         assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
+
+
+@pytest.mark.parametrize("schedule", [None, {"fwd_chunk": 16, "bwd_chunk": 4, "xcd_group": 16, "scatter_rays": 8}])
+def test_bench_workload_full_size(schedule):
+    """The benchmark's own step at its full size: 64 poses x 256 rays x 1024
+    samples with speckle and blur, fused forward + MSE + adjoint replayed from
+    the captured graph (library default schedule, and the one the tuner
+    picks).  Every pose's image, the loss, dL/dZ and every pose gradient
+    against the FP64 oracle; the target is the oracle's render at the offset
+    poses."""
+    from paper_2508_06768_amd.render import FusedStep
+    case = synth.case_batched_c2(B=64)
+    geom, Z, P = _gpu(case)
+    print("case", case.name, "schedule", schedule, flush=True)
+    target = H.oracle_render(case, poses=case.extra["target_poses"])
+    tf = target.astype(np.float32).astype(np.float64)
+    T = torch.from_numpy(tf.astype(np.float32)).to(DEV)
+    step = FusedStep(geom, zero_grad_z=True, schedule=schedule)
+    bm = torch.empty(geom.total, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    gZ = torch.empty_like(Z)
+    gp = torch.empty((geom.n_poses, 6), device=DEV)
+    for _ in range(2):
+        step.step(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+    torch.cuda.synchronize()
+    img = H.oracle_render(case)
+    print("oracle forward done", flush=True)
+    ref_loss = 0.0
+    grad = np.zeros_like(img)
+    for p, f in enumerate(case.fans):
+        o0, o1 = int(geom.offsets[p]), int(geom.offsets[p + 1])
+        d = img[o0:o1] - tf[o0:o1]
+        ref_loss += np.mean(d * d)
+        grad[o0:o1] = 2.0 * d / (o1 - o0)
+    rep = H.parity_report(bm.cpu().numpy(), img, case.fans)
+    print("image", rep, flush=True)
+    assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
+    print("loss", loss.item(), ref_loss, flush=True)
+    assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
+    rV, rp = H.oracle_backward(case, grad)
+    e = H.rel_l2(gZ.cpu().numpy(), rV)
+    print("dZ rel l2", e, flush=True)
+    assert e <= 1e-5
+    gpn = gp.cpu().numpy()
+    worst = max(float(np.abs(gpn[p] - rp[p]).max() / np.linalg.norm(rp[p])) for p in range(len(case.fans)))
+    print("pose worst |error| / |gradient|", worst, flush=True)
+    assert worst <= 1e-5
+    step.close()
 
 
 def test_schedules_agree():
