@@ -41,6 +41,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Plain argument records (the oracle's own; ctypes mirrors them).          */
@@ -730,4 +733,14 @@ int orc_backward(const orc_volume *vol, const double pose[6], const orc_fan *fan
         }
     }
     return 0;
+}
+
+/* Threads the parallel loops above run on (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -80,8 +80,14 @@ def lib():
         _lib.orc_render.restype = ctypes.c_int
         _lib.orc_backward.restype = ctypes.c_int
         _lib.orc_blur_radius.restype = ctypes.c_int
+        _lib.orc_num_threads.restype = ctypes.c_int
         del d
     return _lib
+
+
+def num_threads() -> int:
+    """Threads of the oracle's OpenMP loops."""
+    return int(lib().orc_num_threads())
 
 
 def _dp(a: np.ndarray):
