@@ -73,7 +73,8 @@ enum { DUS_ATTEN_IN_SYSTEM = 0, DUS_ATTEN_POST_HOC = 1, DUS_ATTEN_OFF = 2 };
 #define DUS_MAX_BLUR_RADIUS 32     /* ceil(3 * max(sigma0, sigma1)) */
 
 typedef struct {
-    int32_t nx, ny, nz;            /* voxels per axis, each >= 2 */
+    int32_t nx, ny, nz;            /* voxels per axis, each >= 2; nx * ny * nz < 2^31,
+                                      ny * nz <= 2^24 and nx < 2^24 (DUS_EUNSUPPORTED) */
     float spacing_mm[3];           /* > 0 */
     float origin_mm[3];            /* world position of voxel (0,0,0)'s centre */
 } dus_volume;

@@ -211,11 +211,14 @@ __device__ __forceinline__ void setup_ray(const VolArgs &v, const PhysArgs &p, c
     ray.ds = uniform(ray.ds);
 }
 
-// cell index (clamped) and fraction along one axis; NaN positions clamp to 0
+// cell index (clamped) and fraction along one axis; NaN positions clamp to 0.
+// INSIDE: the caller knows u lies in [0, n-1), where the clamps change
+// nothing.  u >= 0 in both cases, so truncation is the floor.
+template <bool INSIDE>
 __device__ __forceinline__ void axis_cell(double u, int n, int &i0, double &f)
 {
-    const double uc = fmin(fmax(u, 0.0), (double)(n - 1));
-    const int i = min((int)floor(uc), n - 2);
+    const double uc = INSIDE ? u : fmin(fmax(u, 0.0), (double)(n - 1));
+    const int i = INSIDE ? (int)uc : min((int)uc, n - 2);
     i0 = i;
     f = uc - (double)i;
 }
@@ -226,15 +229,34 @@ struct Stencil {
     double fx, fy, fz;
 };
 
+// the volume's ny nz and nx are below 2^24 (checked on the host), so the
+// flat index takes 24-bit multiplies
+template <bool INSIDE = false>
 __device__ __forceinline__ Stencil stencil_at(const VolArgs &v, const Ray &ray, int k)
 {
     Stencil s;
     const double kk = (double)k;
-    axis_cell(fma(kk, ray.du[0], ray.u0[0]), v.nx, s.ix, s.fx);
-    axis_cell(fma(kk, ray.du[1], ray.u0[1]), v.ny, s.iy, s.fy);
-    axis_cell(fma(kk, ray.du[2], ray.u0[2]), v.nz, s.iz, s.fz);
-    s.idx = (s.iz * v.ny + s.iy) * v.nx + s.ix;
+    axis_cell<INSIDE>(fma(kk, ray.du[0], ray.u0[0]), v.nx, s.ix, s.fx);
+    axis_cell<INSIDE>(fma(kk, ray.du[1], ray.u0[1]), v.ny, s.iy, s.fy);
+    axis_cell<INSIDE>(fma(kk, ray.du[2], ray.u0[2]), v.nz, s.iz, s.fz);
+    s.idx = (int)__umul24((unsigned)__umul24((unsigned)s.iz, (unsigned)v.ny) + (unsigned)s.iy, (unsigned)v.nx) + s.ix;
     return s;
+}
+
+// every sample k in [ka, kb] lies in [0, n-1) on every axis: the position is
+// affine in k and its FP64 rounding is monotone, so the two ends decide
+__device__ __forceinline__ bool segment_inside(const VolArgs &v, const Ray &ray, int ka, int kb)
+{
+    const int n[3] = {v.nx, v.ny, v.nz};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double ua = fma((double)ka, ray.du[a], ray.u0[a]);
+        const double ub = fma((double)kb, ray.du[a], ray.u0[a]);
+        const double hi = (double)(n[a] - 1);
+        in = in && (ua >= 0.0) && (ua < hi) && (ub >= 0.0) && (ub < hi);
+    }
+    return in;
 }
 
 __device__ __forceinline__ double lerp(double a, double b, double t) { return fma(t, b - a, a); }
@@ -365,6 +387,31 @@ __device__ __forceinline__ GainK gain_consts(const PhysArgs &p, int S)
     return GainK{S > 1 ? 1.0f / (float)(S - 1) : 0.0f, 1.0f / (float)p.cell};
 }
 
+// speckle multiplier of a pixel at depth fraction zeta, cell fraction fr
+// between the radial cell values x0 and x1, granular variate xg.  zeta^gam
+// with zeta in [1/(S-1), 1] (a normal number); a power below 2^-126 may
+// flush to zero, which leaves the FP32 gain unchanged.
+__device__ __forceinline__ float speckle_mult(const PhysArgs &p, float zeta, float fr, float x0, float x1,
+                                              float xg)
+{
+    const float xr = (1.0f - fr) * x0 + fr * x1;
+    float pw;
+    if (zeta > 0.0f) pw = __builtin_amdgcn_exp2f(p.gam * __builtin_amdgcn_logf(zeta));
+    else pw = (p.gam == 0.0f) ? 1.0f : 0.0f;
+    return 1.0f + p.Ar * pw * (xr - 1.0f) + (p.Ag0 + p.Ag1 * zeta) * (xg - 1.0f);
+}
+
+// radial cell c = k div cell and remainder r of sample k (exact: the
+// reciprocal's quotient is corrected by one step either way)
+__device__ __forceinline__ void cell_of(const PhysArgs &p, const GainK &gk, int k, int &c, int &r)
+{
+    const int cell = p.cell;
+    c = (int)((float)k * gk.inv_cell);
+    r = k - c * cell;
+    if (r < 0) { --c; r += cell; }
+    if (r >= cell) { ++c; r -= cell; }
+}
+
 // Gain of pixel k: post-hoc attenuation (POST) times speckle (SPK), with xg
 // the pixel's granular variate and s_xir the radial cell values of the tile
 // starting at t0.  zeta = k/(S-1) and the cell fraction come from reciprocals
@@ -376,21 +423,10 @@ __device__ __forceinline__ float pixel_gain(const PhysArgs &p, const GainK &gk, 
     float g = 1.0f;
     if (POST) g = exp2f((float)((double)k * (double)postc));
     if (SPK) {
-        const float zeta = (float)k * gk.inv_sm1;
-        const int cell = p.cell;
-        int c = (int)((float)k * gk.inv_cell);
-        int r = k - c * cell;
-        if (r < 0) { --c; r += cell; }
-        if (r >= cell) { ++c; r -= cell; }
-        const float fr = (float)r * gk.inv_cell;
-        const int c_lo = t0 / cell;
-        const float xr = (1.0f - fr) * s_xir[c - c_lo] + fr * s_xir[c + 1 - c_lo];
-        // zeta^gam with zeta in [1/(S-1), 1] (a normal number); a power below
-        // 2^-126 may flush to zero, which leaves the FP32 gain unchanged
-        float pw;
-        if (zeta > 0.0f) pw = __builtin_amdgcn_exp2f(p.gam * __builtin_amdgcn_logf(zeta));
-        else pw = (p.gam == 0.0f) ? 1.0f : 0.0f;
-        g *= 1.0f + p.Ar * pw * (xr - 1.0f) + (p.Ag0 + p.Ag1 * zeta) * (xg - 1.0f);
+        int c, r;
+        cell_of(p, gk, k, c, r);
+        const int c_lo = t0 / p.cell;
+        g *= speckle_mult(p, (float)k * gk.inv_sm1, (float)r * gk.inv_cell, s_xir[c - c_lo], s_xir[c + 1 - c_lo], xg);
     }
     return g;
 }
@@ -415,11 +451,10 @@ __device__ __forceinline__ float posthoc_coef(const PhysArgs &p, float ds)
 // into s_rho[pad8(k - t0)]; optionally keep the samples in s_z, and the
 // last sample of every 256-sample block in s_zc (tile carries).
 // --------------------------------------------------------------------------
-template <int C, bool KEEPZ, bool KEEPG = false>
-__device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, int t0, int S,
-                                            bool absm, int lane, double &zprev, double *s_rho,
-                                            double *s_z, float *s_g = nullptr, double *s_zc = nullptr,
-                                            double *s_dq = nullptr)
+template <int C, bool KEEPZ, bool KEEPG, bool INSIDE>
+__device__ __forceinline__ void gather_tile_body(const VolArgs &v, const Ray &ray, int t0, int S,
+                                                 bool absm, int lane, double &zprev, double *s_rho,
+                                                 double *s_z, float *s_g, double *s_zc, double *s_dq)
 {
     constexpr int T = 64 * C;
     const int sxy = v.nx * v.ny;
@@ -427,7 +462,7 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
     for (int jj = 0; jj < C; ++jj) {
         const int i = jj * 64 + lane;
         const int k = t0 + i;
-        const Stencil st = stencil_at(v, ray, min(k, S - 1));
+        const Stencil st = stencil_at<INSIDE>(v, ray, min(k, S - 1));
         double gu[3];
         const double z = trilinear(v.Z, v.nx, sxy, st, KEEPG ? gu : nullptr);
         double zm = __shfl_up(z, 1);
@@ -453,11 +488,25 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double u = fma(kk, ray.du[a], ray.u0[a]);
-                const bool inside = (u >= 0.0) && (u <= (double)(n[a] - 1));
+                const bool inside = INSIDE || ((u >= 0.0) && (u <= (double)(n[a] - 1)));
                 s_g[a * T + i] = inside ? (float)(gu[a] / (double)v.h[a]) : 0.0f;
             }
         }
     }
+}
+
+template <int C, bool KEEPZ, bool KEEPG = false>
+__device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, int t0, int S,
+                                            bool absm, int lane, double &zprev, double *s_rho,
+                                            double *s_z, float *s_g = nullptr, double *s_zc = nullptr,
+                                            double *s_dq = nullptr)
+{
+    // a tile whose samples all lie inside the volume skips the clamps (the
+    // ray is the same on every lane, so the branch is uniform)
+    if (segment_inside(v, ray, t0, min(t0 + 64 * C - 1, S - 1)))
+        gather_tile_body<C, KEEPZ, KEEPG, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, s_zc, s_dq);
+    else
+        gather_tile_body<C, KEEPZ, KEEPG, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, s_zc, s_dq);
 }
 
 // transfer map of interface rho; invalid (rho = 0, valid = false) -> identity
@@ -675,10 +724,21 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
 #pragma unroll
                 for (int u = 0; u < 4; ++u) gn[4 * q + u] = x[u];
             }
+            // the lane's samples are consecutive: the radial cell index of the
+            // first is exact (cell_of), the others step it
+            int c, r;
+            cell_of(p, gk, t0 + base, c, r);
+            c -= t0 / p.cell;          // index into s_xir
 #pragma unroll
-            for (int i = 0; i < C; ++i)
-                gn[i] = (p.atten == 1) ? pixel_gain<true, true>(p, gk, t0 + base + i, t0, postc, gn[i], s_xir)
-                                       : pixel_gain<true, false>(p, gk, t0 + base + i, t0, postc, gn[i], s_xir);
+            for (int i = 0; i < C; ++i) {
+                const int k = t0 + base + i;
+                float g = speckle_mult(p, (float)k * gk.inv_sm1, (float)r * gk.inv_cell, s_xir[c], s_xir[c + 1], gn[i]);
+                if (p.atten == 1) g *= exp2f((float)((double)k * (double)postc));
+                gn[i] = g;
+                const bool wrap = (r + 1 == p.cell);
+                c += wrap ? 1 : 0;
+                r = wrap ? 0 : r + 1;
+            }
         } else if (p.atten == 1) {
 #pragma unroll
             for (int i = 0; i < C; ++i)
