@@ -121,8 +121,8 @@ def main():
                     help="also launch a plain device copy of 512 MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this renderer build has no multi-GPU path "
-              "(poses shard with no communication; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the renderer has no multi-GPU path "
+              "(poses would shard across GPUs with no communication). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -61,7 +61,7 @@ typedef enum {
     DUS_ESHAPE = -2,       /* sizes out of range or inconsistent */
     DUS_EWORKSPACE = -3,   /* workspace missing or too small */
     DUS_EHIP = -4,         /* a HIP runtime call failed */
-    DUS_EUNSUPPORTED = -5  /* valid request this build does not handle */
+    DUS_EUNSUPPORTED = -5  /* valid request the library does not handle */
 } dus_status;
 
 enum { DUS_REFL_ABS = 0, DUS_REFL_SIGNED = 1 };

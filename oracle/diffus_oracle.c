@@ -19,7 +19,7 @@
  * plus the exact derivative of all of it (the paper's stated purpose,
  * gradient-based registration and reconstruction, Sec. 1 / abstract).
  *
- * Readings of the paper where it is silent (each one is listed in the design doc):
+ * Readings of the paper where it is silent:
  *   - sampling: trilinear at a fixed step ds along each ray, clamp-to-edge
  *     outside the volume, voxel centres at integer index;
  *   - attenuation "in system": every interface step carries a one-way

@@ -1,6 +1,6 @@
 """GPU parity: the HIP renderer (through the C ABI) against the FP64 oracle.
 
-Bars (fixed here, derived in the design doc):
+Bars:
   forward images      per-image relative l2 <= 1e-5, and every pixel within
                       1e-5 of the image's max |value|
   adjoint             dL/dZ relative l2 <= 1e-5 over the volume; dL/dpose per
