@@ -156,7 +156,7 @@ def main():
         from paper_2508_06768_amd.autotune import autotune
         if args.tune_cache:
             os.environ["DUS_AUTOTUNE_CACHE"] = args.tune_cache
-        tune = autotune(step, fused, reps=3, use_cache=bool(args.tune_cache))
+        tune = autotune(step, fused, reps=10, use_cache=bool(args.tune_cache))
         log(f"bench: autotuned schedule {tune['schedule']} ({tune['ms']:.3f} ms)")
     for _ in range(args.warmup):
         fused()

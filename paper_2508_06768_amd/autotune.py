@@ -73,7 +73,7 @@ def _time(fn, reps: int) -> float:
     return a.elapsed_time(b) / reps
 
 
-def autotune(step, run, reps: int = 3, use_cache: bool = True, verbose: bool = False) -> dict:
+def autotune(step, run, reps: int = 10, use_cache: bool = True, verbose: bool = False) -> dict:
     """Pick the fastest schedule for ``step`` (a ``FusedStep``).
 
     run: zero-argument callable that executes one step with the caller's

@@ -509,7 +509,9 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
         gather_tile_body<C, KEEPZ, KEEPG, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, s_zc, s_dq);
 }
 
-// transfer map of interface rho; invalid (rho = 0, valid = false) -> identity
+// transfer map of interface rho (first column and determinant; the second
+// column is (rho, 1)).  VALID = false (interfaces outside [1, S), rho = 0):
+// the identity.
 struct Map {
     double m00, m10, det;
 };
@@ -523,6 +525,17 @@ __device__ __forceinline__ Map make_map(double r, double a2, double sgn, bool va
     m.det = valid ? a2 * (1.0 - r2) : 1.0;
     return m;
 }
+
+// The forward takes every interface's map unselected: with rho = 0 it is
+// diag(a^2, 1), which leaves v1 alone and scales D by a^2.  Past the last
+// sample that changes nothing stored; the interface before sample 0 is the
+// first step of every ray, and its a^2 is taken out of the starting D
+// (d_start).  Dropping the selects cuts the forward's walk and chunk
+// product; the adjoint keeps them (its registers stay within 3 waves).
+__device__ __forceinline__ Map make_map(double r, double a2, double sgn) { return make_map(r, a2, sgn, true); }
+
+// D at the start of a ray for the unselected maps: D = 1 after the first step
+__device__ __forceinline__ double d_start(double a2) { return 1.0 / a2; }
 
 struct Mat {
     double a, b, c, d;     // [[a, b], [c, d]]
@@ -548,8 +561,9 @@ __device__ __forceinline__ Mat shfl_up_mat(const Mat &m, int d)
     return r;
 }
 
-// chunk product Q = M_first ... M_last of a lane's C interfaces, and det
-template <int C>
+// chunk product Q = M_first ... M_last of a lane's C interfaces, and det;
+// SEL: identity maps outside [1, S) (the adjoint), else unselected maps
+template <int C, bool SEL>
 __device__ __forceinline__ void chunk_product(const double *s_rho, int base, int t0, int S,
                                               double a2, double sgn, Mat &Q, double &qd)
 {
@@ -559,9 +573,8 @@ __device__ __forceinline__ void chunk_product(const double *s_rho, int base, int
 #pragma unroll
     for (int i = 0; i < C; ++i) {
         const int k = t0 + base + i;
-        const bool valid = (k >= 1) && (k < S);
         const double r = s_rho[pad8(base + i)];
-        const Map m = make_map(r, a2, sgn, valid);
+        const Map m = make_map(r, a2, sgn, !SEL || ((k >= 1) && (k < S)));
         const double n00 = fma(Q.a, m.m00, Q.b * m.m10);
         const double n01 = fma(Q.a, r, Q.b);
         const double n10 = fma(Q.c, m.m00, Q.d * m.m10);
@@ -638,7 +651,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     const GainK gk = gain_consts(p, fr.n_samples);
     const long long obase = fr.out_offset + (long long)j * S;
 
-    double c0 = 0.0, c1 = 1.0, cD = 1.0, zprev = 0.0;
+    double c0 = 0.0, c1 = 1.0, cD = d_start(a2), zprev = 0.0;
     double piv = 1e300;
     const bool want_piv = (minpiv != nullptr);
     const long long crec = (long long)fr.carry_begin + (long long)j * ((S + kCarryBlock - 1) / kCarryBlock);
@@ -654,7 +667,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
         const int base = lane * C;
         Mat Q, X, Tot;
         double qd, xd, td;
-        chunk_product<C>(s_rho, base, t0, S, a2, sgn, Q, qd);
+        chunk_product<C, false>(s_rho, base, t0, S, a2, sgn, Q, qd);
         scan_exclusive(lane, Q, qd, X, xd, Tot, td);
         int e_last = 0;
         if (carry) {
@@ -673,7 +686,9 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
                 double *q = carry + 4 * r;
                 q[0] = (lane == 0) ? c0 : ldexp(u0, -e);
                 q[1] = (lane == 0) ? c1 : ldexp(u1, -e);
-                q[2] = (lane == 0) ? cD : ldexp(uD, -2 * e);
+                // the ray's first record in the adjoint's convention (identity
+                // map before sample 0): D = 1
+                q[2] = (lane == 0) ? (t0 == 0 ? 1.0 : cD) : ldexp(uD, -2 * e);
                 q[3] = (m == 0) ? zstart : s_zc[m - 1];
                 carry_exp[r] = (m == 0) ? first_rel : e - e_prev;
             }
@@ -685,15 +700,14 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
         float pix[C];
 #pragma unroll
         for (int i = 0; i < C; ++i) {
-            // branch-free: outside [1, S) rho = 0 and the map is the identity,
-            // so the pixel is 0 and the state unchanged
+            // branch-free: outside [1, S) rho = 0, so the pixel is 0 and v1
+            // unchanged (make_map)
             const int k = t0 + base + i;
-            const bool valid = (k >= 1) && (k < S);
             const double r = s_rho[pad8(base + i)];
-            const Map m = make_map(r, a2, sgn, valid);
+            const Map m = make_map(r, a2, sgn);
             const double v1n = fma(v0, r, v1);
             pix[i] = (float)(r * D * rcp64(v1 * v1n));
-            if (want_piv) piv = valid ? fmin(piv, fabs(v1n * rcp64(v1))) : piv;
+            if (want_piv) piv = (k >= 1 && k < S) ? fmin(piv, fabs(v1n * rcp64(v1))) : piv;
             const double v0n = fma(v0, m.m00, v1 * m.m10);
             v0 = v0n;
             v1 = v1n;
@@ -893,7 +907,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             __syncthreads();
             Mat Q, X, Tot;
             double qd, xd, td;
-            chunk_product<C>(s_rho, lane * C, t0, S, a2, sgn, Q, qd);
+            chunk_product<C, true>(s_rho, lane * C, t0, S, a2, sgn, Q, qd);
             scan_exclusive(lane, Q, qd, X, xd, Tot, td);
             const double n0 = fma(c0, Tot.a, c1 * Tot.c);
             const double n1 = fma(c0, Tot.b, c1 * Tot.d);
@@ -965,7 +979,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         const int base = lane * C;
         Mat Q, X, Tot;
         double qd, xd, td;
-        chunk_product<C>(s_rho, base, t0, S, a2, sgn, Q, qd);
+        chunk_product<C, true>(s_rho, base, t0, S, a2, sgn, Q, qd);
         scan_exclusive(lane, Q, qd, X, xd, Tot, td);
         // Walk 1 (forward over the lane's C interfaces): the chunk's affine
         // adjoint map lambda_start = lambda_end J_chunk + f_chunk, with
