@@ -74,7 +74,7 @@ enum { DUS_ATTEN_IN_SYSTEM = 0, DUS_ATTEN_POST_HOC = 1, DUS_ATTEN_OFF = 2 };
 
 typedef struct {
     int32_t nx, ny, nz;            /* voxels per axis, each >= 2; nx * ny * nz < 2^31,
-                                      ny * nz <= 2^24 and nx < 2^24 (DUS_EUNSUPPORTED) */
+                                      nx * ny < 2^24 (else DUS_EUNSUPPORTED) */
     float spacing_mm[3];           /* > 0 */
     float origin_mm[3];            /* world position of voxel (0,0,0)'s centre */
 } dus_volume;

@@ -229,8 +229,8 @@ struct Stencil {
     double fx, fy, fz;
 };
 
-// the volume's ny nz and nx are below 2^24 (checked on the host), so the
-// flat index takes 24-bit multiplies
+// a slice of the volume holds fewer than 2^24 voxels (checked on the host),
+// so the flat index takes two independent 24-bit multiplies
 template <bool INSIDE = false>
 __device__ __forceinline__ Stencil stencil_at(const VolArgs &v, const Ray &ray, int k)
 {
@@ -239,7 +239,7 @@ __device__ __forceinline__ Stencil stencil_at(const VolArgs &v, const Ray &ray, 
     axis_cell<INSIDE>(fma(kk, ray.du[0], ray.u0[0]), v.nx, s.ix, s.fx);
     axis_cell<INSIDE>(fma(kk, ray.du[1], ray.u0[1]), v.ny, s.iy, s.fy);
     axis_cell<INSIDE>(fma(kk, ray.du[2], ray.u0[2]), v.nz, s.iz, s.fz);
-    s.idx = (int)__umul24((unsigned)__umul24((unsigned)s.iz, (unsigned)v.ny) + (unsigned)s.iy, (unsigned)v.nx) + s.ix;
+    s.idx = (int)(__umul24((unsigned)s.iz, (unsigned)(v.nx * v.ny)) + __umul24((unsigned)s.iy, (unsigned)v.nx)) + s.ix;
     return s;
 }
 
@@ -1340,7 +1340,9 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
 #pragma unroll
             for (int q = 0; q < kScatterSpl; ++q) {
                 if (zb[q] == 0.0f) continue;
-                const int l = (st[q].iz - oz) * ps + (st[q].iy - oy) * rs + (st[q].ix - ox);
+                // box offsets and strides stay far below 2^24: 24-bit multiplies
+                const int l = (int)(__umul24((unsigned)(st[q].iz - oz), (unsigned)ps) +
+                                    __umul24((unsigned)(st[q].iy - oy), (unsigned)rs)) + (st[q].ix - ox);
                 if (l != cur && cur >= 0) {
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
@@ -1386,8 +1388,9 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
                     val[u] = 0.0;
                     at[u] = gi[u] = 0;
                     if (e0 + 64 * u + lane < E) {
-                        at[u] = z * ps + y * rs + x;
-                        gi[u] = ((oz + z) * v.ny + (oy + y)) * v.nx + (ox + x);
+                        at[u] = (int)(__umul24((unsigned)z, (unsigned)ps) + __umul24((unsigned)y, (unsigned)rs)) + x;
+                        gi[u] = (int)(__umul24((unsigned)(oz + z), (unsigned)sxy) +
+                                      __umul24((unsigned)(oy + y), (unsigned)v.nx)) + (ox + x);
                         val[u] = s_box[at[u]];
                     }
                     x += dx;

@@ -99,9 +99,9 @@ def test_validation_errors():
     bad.nx = 1
     assert _render(bad, f, 1, p) == _lib.DUS_ESHAPE
     bad = _vol()
-    bad.nx, bad.ny, bad.nz = 2, 4097, 4097        # ny * nz > 2^24: beyond the 24-bit voxel index
+    bad.nx, bad.ny, bad.nz = 4096, 4096, 2        # slice of 2^24 voxels: beyond the 24-bit voxel index
     assert _render(bad, f, 1, p) == _lib.DUS_EUNSUPPORTED
-    bad.nx, bad.ny, bad.nz = 2, 4096, 4096        # ny * nz = 2^24 is accepted (validation only)
+    bad.nx, bad.ny, bad.nz = 4096, 4095, 2        # below 2^24 is accepted (validation only)
     assert L.dus_workspace_bytes(ctypes.byref(bad), f, 1, ctypes.byref(p), 0) >= 0
     bad = _vol()
     bad.spacing_mm = (ctypes.c_float * 3)(1.0, 0.0, 1.0)
