@@ -1,13 +1,13 @@
 """Schedule autotuner for the fused step.
 
 The kernels take a ray-to-wavefront schedule (``dus_schedule``): interfaces
-per lane per tile in the forward (4, 8, 16) and the adjoint (4, 8), and the
-number of consecutive rays kept on one XCD (1..64), and the number of
-neighbouring rays that share one LDS box in the dL/dZ scatter (2, 4, 8).  ``autotune`` times the
-candidates on the caller's actual plan and inputs with HIP events
-(coordinate descent: forward chunk, then adjoint chunk, then XCD grouping),
-installs the fastest on the plan and remembers it in a JSON cache keyed by
-GPU architecture and a shape class of the workload.
+per lane per tile in the forward (4, 8, 16) and the adjoint (4, 8), the
+number of neighbouring rays that share one LDS box in the dL/dZ scatter (2,
+4, 8), and the number of consecutive rays kept on one XCD (1..64).
+``autotune`` times the candidates on the caller's actual plan and inputs
+with HIP events (coordinate descent in that order, each candidate over
+``reps`` steps), installs the fastest on the plan and remembers it in a JSON
+cache keyed by GPU architecture and a shape class of the workload.
 
 Cache file: ``$DUS_AUTOTUNE_CACHE`` or ``~/.cache/diffus_autotune.json``.
 """
