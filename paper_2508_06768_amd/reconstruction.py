@@ -80,10 +80,13 @@ def main(argv=None) -> None:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--weight", type=float, default=1e-5)
-    ap.add_argument("--init", choices=["blur", "bump"], default="blur",
-                    help="start from the volume blurred, or with a Gaussian bump added inside the footprint")
+    ap.add_argument("--init", choices=["blur", "bump", "cube"], default="blur",
+                    help="start from the volume blurred, with a Gaussian bump added inside the footprint, "
+                         "or with a cube of the footprint scaled (sharp faces)")
     ap.add_argument("--init-sigma", type=float, default=2.0, help="blur of the starting volume (voxels)")
     ap.add_argument("--bump", type=float, default=0.05, help="bump amplitude (MRayl); radius 3 voxels")
+    ap.add_argument("--cube", type=int, default=8, help="cube side (voxels) for --init cube")
+    ap.add_argument("--cube-scale", type=float, default=1.05, help="impedance factor inside the cube")
     ap.add_argument("--refl", choices=["abs", "signed"], default="signed")
     ap.add_argument("--effects", action="store_true", help="speckle and blur in the renders")
     ap.add_argument("--seed", type=int, default=1007)
@@ -108,17 +111,24 @@ def main(argv=None) -> None:
         Z0 = torch.from_numpy(gaussian_filter(gt, args.init_sigma, mode="nearest").astype(np.float32)).to(dev)
         region = mask
     else:
-        # a Gaussian bump centred on the footprint voxel seen by the most poses
+        # the perturbation sits at the footprint voxel seen by the most poses
         cover = torch.zeros(gt.shape, dtype=torch.int32, device=dev)
         for p in range(args.poses):
             g1 = Geometry(gt.shape, (h,) * 3, (0.0,) * 3, [fans[p]], phys)
             cover += footprint_mask(poses[p:p + 1].contiguous(), g1).int()
         c = np.unravel_index(int(torch.argmax(cover).item()), gt.shape)
         iz, iy, ix = np.meshgrid(*[np.arange(k) for k in gt.shape], indexing="ij")
-        r2 = (iz - c[0]) ** 2 + (iy - c[1]) ** 2 + (ix - c[2]) ** 2
-        bump = (args.bump * np.exp(-r2 / (2 * 3.0 ** 2))).astype(np.float32)
-        Z0 = torch.from_numpy(gt + bump).to(dev)
-        region = torch.from_numpy(bump > 0.1 * args.bump).to(dev)
+        if args.init == "bump":
+            r2 = (iz - c[0]) ** 2 + (iy - c[1]) ** 2 + (ix - c[2]) ** 2
+            bump = (args.bump * np.exp(-r2 / (2 * 3.0 ** 2))).astype(np.float32)
+            Z0 = torch.from_numpy(gt + bump).to(dev)
+            region = torch.from_numpy(bump > 0.1 * args.bump).to(dev)
+        else:
+            lo = [int(ci) - args.cube // 2 for ci in c]
+            inside = ((iz >= lo[0]) & (iz < lo[0] + args.cube) & (iy >= lo[1]) & (iy < lo[1] + args.cube) &
+                      (ix >= lo[2]) & (ix < lo[2] + args.cube))
+            Z0 = torch.from_numpy(np.where(inside, gt * np.float32(args.cube_scale), gt).astype(np.float32)).to(dev)
+            region = torch.from_numpy(inside).to(dev)
 
     def err(Z):
         # l2 error on the footprint (blurred start) or on the bump
@@ -131,8 +141,10 @@ def main(argv=None) -> None:
     out = {
         "workload": f"{args.poses} poses x {args.rays} rays x {args.samples} samples, {args.n}^3 volume at "
                     f"{h:g} mm, {args.refl} reflection{', speckle + blur' if args.effects else ''}, start: "
-                    + (f"the volume blurred by {args.init_sigma:g} voxels" if args.init == "blur" else
-                       f"the volume plus a {args.bump:g} MRayl Gaussian bump (3 voxels) in the footprint")
+                    + {"blur": f"the volume blurred by {args.init_sigma:g} voxels",
+                       "bump": f"the volume plus a {args.bump:g} MRayl Gaussian bump (3 voxels) in the footprint",
+                       "cube": f"the volume with a {args.cube}-voxel cube in the footprint scaled by "
+                               f"{args.cube_scale:g}"}[args.init]
                     + f"; fused step + smoothness "
                     f"(weight {args.weight:g}) + Adam (lr {args.lr:g}), {args.steps} steps",
         "ray_samples_per_step": int(geom.total),
@@ -142,7 +154,7 @@ def main(argv=None) -> None:
         "ms_per_step": res.ms_per_step,
         "loss_first": float(res.loss_history[0]),
         "loss_last": float(res.loss_history[-1]),
-        "error_region": "footprint" if args.init == "blur" else "bump",
+        "error_region": {"blur": "footprint", "bump": "bump", "cube": "cube"}[args.init],
         "error_region_voxels": int(region.sum().item()),
         "error_l2_first": e0,
         "error_l2_last": e1,
