@@ -221,6 +221,38 @@ int dus_adam_step(float *x, const float *grad, float *m, float *v, int64_t n, fl
                   float beta2, float eps, int32_t t, float lo, float hi, void *stream);
 
 /*
+ * Impedance mapping (Sec. 2.2: the paper turns MRI or CT intensities into an
+ * impedance volume voxel by voxel, with a learned or tabulated map).  Here
+ * the map is a piecewise-linear table of n knots (x_j, z_j), x strictly
+ * increasing, constant beyond its ends:
+ *   Z = z_0 for v <= x_0,  z_{n-1} for v >= x_{n-1},
+ *   Z = z_j + t (z_{j+1} - z_j), t = (v - x_j) / (x_{j+1} - x_j) for
+ *   x_j <= v < x_{j+1}; NaN stays NaN.
+ * The renderer needs Z > 0, which positive z_j give.  The table is a HOST
+ * record (2 <= n <= DUS_MAX_KNOTS, finite values, else DUS_EINVAL);
+ * intensities and Z are DEVICE FP32 arrays of n_vox elements.  The
+ * calibration itself (the paper's training pairs and MLP) is not given.
+ */
+#define DUS_MAX_KNOTS 64
+typedef struct {
+    int32_t n;
+    float x[DUS_MAX_KNOTS];        /* intensities, strictly increasing */
+    float z[DUS_MAX_KNOTS];        /* impedances (MRayl) */
+} dus_lut;
+
+int dus_map_impedance(const float *intensity, int64_t n_vox, const dus_lut *lut, float *Z, void *stream);
+
+/*
+ * Adjoint of dus_map_impedance for dL/dZ (device FP32, n_vox):
+ *   grad_intensity (device FP32 or NULL, overwritten):
+ *     dL/dZ (z_{j+1} - z_j) / (x_{j+1} - x_j) inside the table (the segment to
+ *     the right at a knot), 0 beyond its ends;
+ *   grad_z (device FP64 [lut->n] or NULL, +=): dL/dz_j summed over the voxels.
+ */
+int dus_map_impedance_backward(const float *intensity, int64_t n_vox, const dus_lut *lut, const float *grad_Z,
+                               float *grad_intensity, double *grad_z, void *stream);
+
+/*
  * Footprint of the rendering: mask[v] = 1 for every voxel v that is a corner
  * of the trilinear stencil of some sample of some ray (other entries are left
  * untouched).  mask: device uint8 [nz][ny][nx].  Used to count the distinct

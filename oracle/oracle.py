@@ -277,6 +277,47 @@ def smoothness(Z, spacing, weight: float):
     return R, g
 
 
+def map_impedance(v, xk, zk):
+    """Impedance mapping (Sec. 2.2: intensities to impedance, voxel by voxel)
+    as a piecewise-linear table, written from its definition: z_0 at or
+    below x_0, z_{n-1} at or above x_{n-1}, and for x_j <= v < x_{j+1}
+    Z = z_j + t (z_{j+1} - z_j) with t = (v - x_j) / (x_{j+1} - x_j).
+    Also returns dZ/dv (the slope of the segment to the right at a knot, 0
+    beyond the ends).  NaN stays NaN.  FP64."""
+    v = np.asarray(v, dtype=np.float64)
+    xk = np.asarray(xk, dtype=np.float64)
+    zk = np.asarray(zk, dtype=np.float64)
+    Z = np.full(v.shape, np.nan)
+    dv = np.zeros(v.shape)
+    Z[v <= xk[0]] = zk[0]
+    Z[v >= xk[-1]] = zk[-1]
+    for j in range(len(xk) - 1):
+        sel = (v >= xk[j]) & (v < xk[j + 1]) & (v > xk[0])
+        t = (v[sel] - xk[j]) / (xk[j + 1] - xk[j])
+        Z[sel] = zk[j] + t * (zk[j + 1] - zk[j])
+        dv[sel] = (zk[j + 1] - zk[j]) / (xk[j + 1] - xk[j])
+    return Z, dv
+
+
+def map_impedance_grad(v, xk, zk, gZ):
+    """Adjoint of map_impedance for dL/dZ = gZ: (dL/dv, dL/dz_j).  Each voxel
+    hands (1 - t) gZ to z_j and t gZ to z_{j+1} inside segment j, all of gZ
+    to the end knot beyond an end."""
+    v = np.asarray(v, dtype=np.float64)
+    gZ = np.asarray(gZ, dtype=np.float64)
+    xk = np.asarray(xk, dtype=np.float64)
+    _, dv = map_impedance(v, xk, zk)
+    gz = np.zeros(len(xk))
+    gz[0] += gZ[v <= xk[0]].sum()
+    gz[-1] += gZ[v >= xk[-1]].sum()
+    for j in range(len(xk) - 1):
+        sel = (v >= xk[j]) & (v < xk[j + 1]) & (v > xk[0])
+        t = (v[sel] - xk[j]) / (xk[j + 1] - xk[j])
+        gz[j] += ((1.0 - t) * gZ[sel]).sum()
+        gz[j + 1] += (t * gZ[sel]).sum()
+    return gZ * dv, gz
+
+
 def adam(x, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float, lo: float, hi: float):
     """One Adam step (Kingma and Ba, 2015) with the result clamped to
     [lo, hi]; returns (x, m, v) as new arrays (FP64)."""

@@ -51,6 +51,13 @@ class DusGrid2d(ctypes.Structure):
                 ("dx_mm", ctypes.c_float), ("dz_mm", ctypes.c_float), ("fill", ctypes.c_float)]
 
 
+MAX_KNOTS = 64
+
+
+class DusLut(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("x", ctypes.c_float * MAX_KNOTS), ("z", ctypes.c_float * MAX_KNOTS)]
+
+
 # every symbol include/diffus.h declares, with (restype, argtypes)
 SIGNATURES = {
     "dus_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -68,6 +75,8 @@ SIGNATURES = {
     "dus_sample_volume": (ctypes.c_int, [c_vp, ctypes.POINTER(DusVolume), c_vp, ctypes.POINTER(DusFan), c_i32,
                                          c_vp, c_vp]),
     "dus_scan_convert": (ctypes.c_int, [c_vp, ctypes.POINTER(DusFan), ctypes.POINTER(DusGrid2d), c_vp, c_vp]),
+    "dus_map_impedance": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(DusLut), c_vp, c_vp]),
+    "dus_map_impedance_backward": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(DusLut), c_vp, c_vp, c_vp, c_vp]),
     "dus_smoothness_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(DusVolume)]),
     "dus_smoothness": (ctypes.c_int, [c_vp, ctypes.POINTER(DusVolume), ctypes.c_float, c_vp, c_vp, c_vp, c_sz,
                                       c_vp]),

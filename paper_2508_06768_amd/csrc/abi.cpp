@@ -568,6 +568,49 @@ int dus_adam_step(float *x, const float *grad, float *m, float *v, int64_t n, fl
     return DUS_OK;
 }
 
+static int lut_args(const dus_lut *lut, dus::LutArgs &a)
+{
+    if (!lut) return fail(DUS_EINVAL, "lut is NULL");
+    static_assert(DUS_MAX_KNOTS == dus::kMaxKnots, "knot limit");
+    if (lut->n < 2 || lut->n > DUS_MAX_KNOTS) return fail(DUS_EINVAL, "lut needs 2..DUS_MAX_KNOTS knots");
+    a = dus::LutArgs{};
+    a.n = lut->n;
+    for (int j = 0; j < lut->n; ++j) {
+        if (!finite_f(lut->x[j]) || !finite_f(lut->z[j])) return fail(DUS_EINVAL, "lut values must be finite");
+        if (j > 0 && !(lut->x[j] > lut->x[j - 1])) return fail(DUS_EINVAL, "lut x must be strictly increasing");
+        a.x[j] = lut->x[j];
+        a.z[j] = lut->z[j];
+    }
+    return DUS_OK;
+}
+
+int dus_map_impedance(const float *intensity, int64_t n_vox, const dus_lut *lut, float *Z, void *stream)
+{
+    dus::LutArgs a;
+    int s;
+    if ((s = lut_args(lut, a)) != DUS_OK) return s;
+    if (n_vox < 0) return fail(DUS_ESHAPE, "n_vox < 0");
+    if (n_vox == 0) return DUS_OK;
+    if (!intensity || !Z) return fail(DUS_EINVAL, "NULL pointer");
+    DUS_HIP(dus::launch_map(intensity, n_vox, a, Z, reinterpret_cast<hipStream_t>(stream)), "map kernel launch");
+    return DUS_OK;
+}
+
+int dus_map_impedance_backward(const float *intensity, int64_t n_vox, const dus_lut *lut, const float *grad_Z,
+                               float *grad_intensity, double *grad_z, void *stream)
+{
+    dus::LutArgs a;
+    int s;
+    if ((s = lut_args(lut, a)) != DUS_OK) return s;
+    if (n_vox < 0) return fail(DUS_ESHAPE, "n_vox < 0");
+    if (n_vox == 0 || (!grad_intensity && !grad_z)) return DUS_OK;
+    if (!intensity || !grad_Z) return fail(DUS_EINVAL, "NULL pointer");
+    DUS_HIP(dus::launch_map_backward(intensity, n_vox, a, grad_Z, grad_intensity, grad_z,
+                                     reinterpret_cast<hipStream_t>(stream)),
+            "map adjoint kernel launch");
+    return DUS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // plan: batched fused forward + MSE + adjoint, replayed from a HIP graph
 // ---------------------------------------------------------------------------

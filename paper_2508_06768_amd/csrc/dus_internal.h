@@ -120,6 +120,17 @@ hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, 
                        float eps, float c1, float c2, float lo, float hi, hipStream_t st);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t st);
+// impedance mapping: piecewise-linear table from intensity to impedance
+constexpr int kMaxKnots = 64;
+struct LutArgs {
+    int n;                      // knots, 2..kMaxKnots, x strictly increasing
+    float x[kMaxKnots];
+    float z[kMaxKnots];
+};
+hipError_t launch_map(const float *in, int64_t n, const LutArgs &lut, float *Z, hipStream_t st);
+// grad_in (nullable): overwritten; grad_z (nullable): += per knot (FP64)
+hipError_t launch_map_backward(const float *in, int64_t n, const LutArgs &lut, const float *gZ, float *grad_in,
+                               double *grad_z, hipStream_t st);
 hipError_t launch_pixel_gain(const PhysArgs &p, const FanRec &f, float *out, hipStream_t st);
 
 }  // namespace dus

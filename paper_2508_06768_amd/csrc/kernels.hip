@@ -1785,6 +1785,96 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ x, const float
     }
 }
 
+// --------------------------------------------------------------------------
+// impedance mapping (Sec. 2.2): the paper turns MRI or CT intensities into
+// impedance voxel by voxel.  Here the map is a piecewise-linear table
+// (x_j, z_j), constant beyond its ends; a voxel of intensity v in
+// [x_j, x_{j+1}) maps to z_j + t (z_{j+1} - z_j), t = (v - x_j) / (x_{j+1} - x_j).
+// --------------------------------------------------------------------------
+// segment j of v (x_j <= v < x_{j+1}, 0 <= j <= n - 2), binary search in LDS
+__device__ __forceinline__ int lut_segment(const float *sx, int n, float v)
+{
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (v >= sx[mid]) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_map(const float *__restrict__ in, long long n, LutArgs lut,
+                                             float *__restrict__ Z)
+{
+    __shared__ float s_x[kMaxKnots], s_z[kMaxKnots];
+    const int m = lut.n;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        s_x[i] = lut.x[i];
+        s_z[i] = lut.z[i];
+    }
+    __syncthreads();
+    const float x0 = s_x[0], xn = s_x[m - 1];
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const float v = in[i];
+        float z;
+        if (v <= x0) z = s_z[0];
+        else if (v >= xn) z = s_z[m - 1];
+        else {
+            // NaN fails both tests above and stays NaN here
+            const int j = lut_segment(s_x, m, v);
+            const float t = __fdiv_rn(v - s_x[j], s_x[j + 1] - s_x[j]);
+            z = fmaf(t, s_z[j + 1] - s_z[j], s_z[j]);
+        }
+        Z[i] = z;
+    }
+}
+
+// dL/dv = dL/dZ (z_{j+1} - z_j) / (x_{j+1} - x_j) inside the table (the right
+// segment at a knot), 0 beyond its ends; dL/dz_j += (1 - t) dL/dZ and
+// dL/dz_{j+1} += t dL/dZ, or all of dL/dZ to the end knot beyond an end.
+// The knot sums go through an FP64 LDS copy per block, then one global FP64
+// atomic per knot and block.
+__global__ __launch_bounds__(256) void k_map_backward(const float *__restrict__ in, long long n, LutArgs lut,
+                                                      const float *__restrict__ gZ, float *__restrict__ grad_in,
+                                                      double *__restrict__ grad_z)
+{
+    __shared__ float s_x[kMaxKnots], s_z[kMaxKnots];
+    __shared__ double s_g[kMaxKnots];
+    const int m = lut.n;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        s_x[i] = lut.x[i];
+        s_z[i] = lut.z[i];
+        s_g[i] = 0.0;
+    }
+    __syncthreads();
+    const float x0 = s_x[0], xn = s_x[m - 1];
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const float v = in[i];
+        const float g = gZ[i];
+        float gi = 0.0f;
+        if (v <= x0) {
+            if (grad_z) atomicAdd(&s_g[0], (double)g);
+        } else if (v >= xn) {
+            if (grad_z) atomicAdd(&s_g[m - 1], (double)g);
+        } else {
+            const int j = lut_segment(s_x, m, v);
+            const float dx = s_x[j + 1] - s_x[j];
+            gi = g * __fdiv_rn(s_z[j + 1] - s_z[j], dx);
+            if (grad_z) {
+                const double t = (double)__fdiv_rn(v - s_x[j], dx);
+                atomicAdd(&s_g[j], (1.0 - t) * (double)g);
+                atomicAdd(&s_g[j + 1], t * (double)g);
+            }
+        }
+        if (grad_in) grad_in[i] = gi;
+    }
+    if (grad_z) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < m; k += 256)
+            if (s_g[k] != 0.0) atomicAdd(grad_z + k, s_g[k]);
+    }
+}
+
 __global__ void k_copy_f64(const double *s, double *d, long long n)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -2065,6 +2155,24 @@ hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, 
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_adam, dim3(grid_for(n, 256)), dim3(256), 0, st, x, g, m, v, (long long)n, lr, b1, b2,
                        eps, c1, c2, lo, hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_map(const float *in, int64_t n, const LutArgs &lut, float *Z, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map, dim3(grid_for(n, 256)), dim3(256), 0, st, in, (long long)n, lut, Z);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_backward(const float *in, int64_t n, const LutArgs &lut, const float *gZ, float *grad_in,
+                               double *grad_z, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    // at most 4096 blocks: one FP64 global atomic per knot and block
+    int g = grid_for(n, 256);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_map_backward, dim3(g), dim3(256), 0, st, in, (long long)n, lut, gZ, grad_in, grad_z);
     return hipGetLastError();
 }
 

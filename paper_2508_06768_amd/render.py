@@ -281,6 +281,45 @@ def adam_step(x: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Ten
           "dus_adam_step")
 
 
+def lut_record(x, z) -> _lib.DusLut:
+    """Piecewise-linear intensity -> impedance table as the ABI's record."""
+    x = np.asarray(x, dtype=np.float32).reshape(-1)
+    z = np.asarray(z, dtype=np.float32).reshape(-1)
+    if x.shape != z.shape or not 2 <= x.size <= _lib.MAX_KNOTS:
+        raise ValueError(f"the table needs 2..{_lib.MAX_KNOTS} (x, z) pairs of equal length")
+    r = _lib.DusLut()
+    r.n = int(x.size)
+    for j in range(x.size):
+        r.x[j], r.z[j] = float(x[j]), float(z[j])
+    return r
+
+
+def map_impedance(intensity: torch.Tensor, lut_x, lut_z, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Impedance volume from an intensity volume through the piecewise-linear
+    table (lut_x, lut_z), constant beyond its ends."""
+    _check_buffer(intensity, "intensity", 0)
+    if out is None:
+        out = torch.empty_like(intensity)
+    _check_buffer(out, "out", intensity.numel(), device=intensity.device)
+    lut = lut_record(lut_x, lut_z)
+    check(_lib.lib().dus_map_impedance(_ptr(intensity), intensity.numel(), ctypes.byref(lut), _ptr(out), _stream()),
+          "dus_map_impedance")
+    return out
+
+
+def map_impedance_backward(intensity: torch.Tensor, lut_x, lut_z, grad_Z: torch.Tensor, want_intensity: bool = True,
+                           want_table: bool = True):
+    """(dL/dintensity, dL/dz_j) of map_impedance for dL/dZ."""
+    _check_buffer(intensity, "intensity", 0)
+    _check_buffer(grad_Z, "grad_Z", intensity.numel(), device=intensity.device)
+    lut = lut_record(lut_x, lut_z)
+    gi = torch.empty_like(intensity) if want_intensity else None
+    gz = torch.zeros(lut.n, dtype=torch.float64, device=intensity.device) if want_table else None
+    check(_lib.lib().dus_map_impedance_backward(_ptr(intensity), intensity.numel(), ctypes.byref(lut), _ptr(grad_Z),
+                                                _ptr(gi), _ptr(gz), _stream()), "dus_map_impedance_backward")
+    return gi, gz
+
+
 def footprint_mask(poses: torch.Tensor, geom: Geometry) -> torch.Tensor:
     """uint8 [nz][ny][nx]: 1 on every voxel of some trilinear stencil."""
     nz, ny, nx = geom.shape

@@ -39,13 +39,15 @@ def test_record_layout_matches_header(tmp_path):
     src.write_text('#include "diffus.h"\n#include <stdio.h>\n#include <stddef.h>\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dus_volume), sizeof(dus_fan),'
                    ' sizeof(dus_physics), sizeof(dus_schedule), offsetof(dus_fan, out_offset),'
-                   ' offsetof(dus_physics, seed), sizeof(dus_grid2d), offsetof(dus_grid2d, fill)); return 0;}\n')
+                   ' offsetof(dus_physics, seed), sizeof(dus_grid2d), offsetof(dus_grid2d, fill));'
+                   ' printf("%zu %zu\\n", sizeof(dus_lut), offsetof(dus_lut, z)); return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(DusVolume), ctypes.sizeof(DusFan), ctypes.sizeof(DusPhysics),
             ctypes.sizeof(_lib.DusSchedule), DusFan.out_offset.offset, DusPhysics.seed.offset,
-            ctypes.sizeof(_lib.DusGrid2d), _lib.DusGrid2d.fill.offset]
+            ctypes.sizeof(_lib.DusGrid2d), _lib.DusGrid2d.fill.offset, ctypes.sizeof(_lib.DusLut),
+            _lib.DusLut.z.offset]
     assert got == want
 
 
@@ -200,6 +202,26 @@ def test_schedule_validation():
         assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays) == (16, 8, 64, 2)
     finally:
         L.dus_set_schedule(ctypes.byref(old))
+
+
+def test_map_impedance_validation():
+    L = _lib.lib()
+    lut = _lib.DusLut()
+    lut.n = 1
+    assert L.dus_map_impedance(FAKE, 10, ctypes.byref(lut), FAKE, None) == _lib.DUS_EINVAL
+    lut.n = 3
+    for j, (x, z) in enumerate(((0.0, 1.0), (1.0, 2.0), (1.0, 3.0))):      # x not increasing
+        lut.x[j], lut.z[j] = x, z
+    assert L.dus_map_impedance(FAKE, 10, ctypes.byref(lut), FAKE, None) == _lib.DUS_EINVAL
+    lut.x[2] = 2.0
+    lut.z[1] = float("inf")
+    assert L.dus_map_impedance(FAKE, 10, ctypes.byref(lut), FAKE, None) == _lib.DUS_EINVAL
+    lut.z[1] = 2.0
+    assert L.dus_map_impedance(FAKE, -1, ctypes.byref(lut), FAKE, None) == _lib.DUS_ESHAPE
+    assert L.dus_map_impedance(None, 10, ctypes.byref(lut), FAKE, None) == _lib.DUS_EINVAL
+    assert L.dus_map_impedance(FAKE, 0, ctypes.byref(lut), FAKE, None) == _lib.DUS_OK
+    assert L.dus_map_impedance_backward(FAKE, 10, None, FAKE, FAKE, None, None) == _lib.DUS_EINVAL
+    assert L.dus_map_impedance_backward(FAKE, 10, ctypes.byref(lut), None, FAKE, None, None) == _lib.DUS_EINVAL
 
 
 def test_binding_refuses_host_buffers():

@@ -261,3 +261,32 @@ def test_adam_matches_oracle():
     np.testing.assert_allclose(m.cpu().numpy(), rm, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(v.cpu().numpy(), rv, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(x.cpu().numpy(), rx, rtol=1e-6, atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# impedance mapping (Sec. 2.2)
+# --------------------------------------------------------------------------
+def test_map_impedance_matches_oracle():
+    """Piecewise-linear intensity -> impedance table: values, dL/dintensity
+    and dL/dz_j against the oracle on intensities below, inside and above
+    the table and exactly at its knots (FP32 arithmetic on the GPU)."""
+    from oracle import oracle as O
+    from paper_2508_06768_amd.render import map_impedance, map_impedance_backward
+    rng = np.random.default_rng(31)
+    xk = np.cumsum(rng.uniform(20.0, 200.0, 12)).astype(np.float32) - 500.0   # CT-like numbers
+    zk = rng.uniform(1.3, 7.8, 12).astype(np.float32)
+    v = rng.uniform(float(xk[0]) - 100.0, float(xk[-1]) + 100.0, 300_001).astype(np.float32)
+    v[:12] = xk
+    gZ = rng.standard_normal(v.size).astype(np.float32)
+    I = torch.from_numpy(v).to(DEV)
+    Zg = map_impedance(I, xk, zk).cpu().numpy().astype(np.float64)
+    gi, gz = map_impedance_backward(I, xk, zk, torch.from_numpy(gZ).to(DEV))
+    Zr, _ = O.map_impedance(v.astype(np.float64), xk.astype(np.float64), zk.astype(np.float64))
+    gir, gzr = O.map_impedance_grad(v.astype(np.float64), xk.astype(np.float64), zk.astype(np.float64),
+                                    gZ.astype(np.float64))
+    tol = 8 * np.finfo(np.float32).eps
+    assert np.all(np.abs(Zg - Zr) <= tol * np.abs(zk).max())
+    gin = gi.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(gin - gir) <= tol * np.abs(gir).max())
+    np.testing.assert_allclose(gz.cpu().numpy(), gzr, rtol=1e-5, atol=1e-6 * np.abs(gzr).max())
+

@@ -570,3 +570,49 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(x, want, rtol=1e-12)
     np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
     np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# impedance mapping (Sec. 2.2) as a piecewise-linear table
+# --------------------------------------------------------------------------
+def test_map_impedance_closed_form():
+    """Table (0, 1), (1, 2), (3, 6): values worked by hand, the ends held
+    constant, the slope of the right-hand segment at a knot."""
+    v = np.array([-1.0, 0.0, 0.5, 1.0, 2.0, 2.999, 3.0, 5.0, np.nan])
+    Z, dv = O.map_impedance(v, [0.0, 1.0, 3.0], [1.0, 2.0, 6.0])
+    want = [1.0, 1.0, 1.5, 2.0, 4.0, 5.998, 6.0, 6.0]
+    assert np.allclose(Z[:8], want, rtol=0, atol=1e-12) and np.isnan(Z[8])
+    assert list(dv[:8]) == [0.0, 0.0, 1.0, 2.0, 2.0, 2.0, 0.0, 0.0]
+    # a two-knot identity table is the clamp
+    w = np.linspace(-2.0, 7.0, 91)
+    Zi, dvi = O.map_impedance(w, [1.5, 4.0], [1.5, 4.0])
+    assert np.allclose(Zi, np.clip(w, 1.5, 4.0), rtol=0, atol=1e-12)
+    assert np.all(dvi == np.where((w > 1.5) & (w < 4.0), 1.0, 0.0))
+
+
+def test_map_impedance_adjoint_linearity_and_differences():
+    """The map is linear in the table values: the table gradient equals exact
+    differences in z_j; each voxel's weights sum to one; dZ/dv matches
+    central differences away from the knots."""
+    rng = np.random.default_rng(7)
+    xk = np.cumsum(rng.uniform(0.2, 1.0, 9))
+    zk = rng.uniform(1.3, 8.0, 9)
+    v = rng.uniform(xk[0] - 1.0, xk[-1] + 1.0, 2000)
+    v[:9] = xk                                   # exactly at the knots
+    gZ = rng.standard_normal(v.size)
+    gv, gz = O.map_impedance_grad(v, xk, zk, gZ)
+    Z0, _ = O.map_impedance(v, xk, zk)
+    for j in range(len(xk)):
+        e = np.zeros(len(xk))
+        e[j] = 1.0
+        Zj, _ = O.map_impedance(v, xk, zk + e)
+        assert np.dot(gZ, Zj - Z0) == pytest.approx(gz[j], rel=1e-12, abs=1e-12)
+    _, ones = O.map_impedance_grad(v, xk, zk, np.ones(v.size))
+    assert ones.sum() == pytest.approx(v.size, rel=1e-14)
+    h = 1e-6
+    far = np.min(np.abs(v[:, None] - xk[None, :]), axis=1) > 10 * h
+    Zp, _ = O.map_impedance(v + h, xk, zk)
+    Zm, _ = O.map_impedance(v - h, xk, zk)
+    fd = (Zp - Zm) / (2 * h)
+    assert np.allclose(gv[far], gZ[far] * fd[far], rtol=1e-6, atol=1e-9)
+
