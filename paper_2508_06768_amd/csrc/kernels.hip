@@ -1791,16 +1791,29 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ x, const float
 // (x_j, z_j), constant beyond its ends; a voxel of intensity v in
 // [x_j, x_{j+1}) maps to z_j + t (z_{j+1} - z_j), t = (v - x_j) / (x_{j+1} - x_j).
 // --------------------------------------------------------------------------
-// segment j of v (x_j <= v < x_{j+1}, 0 <= j <= n - 2), binary search in LDS
-__device__ __forceinline__ int lut_segment(const float *sx, int n, float v)
+// segment j of v (x_j <= v < x_{j+1}, 0 <= j <= n - 2) for x_0 < v < x_{n-1}:
+// branch-free search in LDS, one halving step per bit of n - 2 (top: the
+// largest power of two <= n - 2, or 0 when n = 2)
+__device__ __forceinline__ int lut_segment(const float *sx, int top, int n, float v)
 {
-    int lo = 0, hi = n - 1;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (v >= sx[mid]) lo = mid;
-        else hi = mid;
+    int j = 0;
+    for (int s = top; s > 0; s >>= 1) {
+        const int c = j + s;
+        j = (c <= n - 2 && v >= sx[c]) ? c : j;
     }
-    return lo;
+    return j;
+}
+
+__device__ __forceinline__ int lut_top(int n) { return n > 2 ? 1 << (31 - __builtin_clz(n - 2)) : 0; }
+
+__device__ __forceinline__ float lut_eval(const float *sx, const float *sz, int top, int n, float v)
+{
+    if (v <= sx[0]) return sz[0];
+    if (v >= sx[n - 1]) return sz[n - 1];
+    // NaN fails both tests above and stays NaN here
+    const int j = lut_segment(sx, top, n, v);
+    const float t = __fdiv_rn(v - sx[j], sx[j + 1] - sx[j]);
+    return fmaf(t, sz[j + 1] - sz[j], sz[j]);
 }
 
 __global__ __launch_bounds__(256) void k_map(const float *__restrict__ in, long long n, LutArgs lut,
@@ -1813,19 +1826,23 @@ __global__ __launch_bounds__(256) void k_map(const float *__restrict__ in, long 
         s_z[i] = lut.z[i];
     }
     __syncthreads();
-    const float x0 = s_x[0], xn = s_x[m - 1];
-    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
-        const float v = in[i];
-        float z;
-        if (v <= x0) z = s_z[0];
-        else if (v >= xn) z = s_z[m - 1];
-        else {
-            // NaN fails both tests above and stays NaN here
-            const int j = lut_segment(s_x, m, v);
-            const float t = __fdiv_rn(v - s_x[j], s_x[j + 1] - s_x[j]);
-            z = fmaf(t, s_z[j + 1] - s_z[j], s_z[j]);
+    const int top = lut_top(m);
+    // four voxels per thread and pass, one grid stride apart: their loads
+    // and searches are independent
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long i0 = (long long)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += 4 * stride) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long long i = i0 + u * stride;
+            v[u] = (i < n) ? in[i] : 0.0f;
         }
-        Z[i] = z;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const long long i = i0 + u * stride;
+            const float z = lut_eval(s_x, s_z, top, m, v[u]);
+            if (i < n) Z[i] = z;
+        }
     }
 }
 
@@ -1848,6 +1865,7 @@ __global__ __launch_bounds__(256) void k_map_backward(const float *__restrict__ 
     }
     __syncthreads();
     const float x0 = s_x[0], xn = s_x[m - 1];
+    const int top = lut_top(m);
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
         const float v = in[i];
         const float g = gZ[i];
@@ -1857,7 +1875,7 @@ __global__ __launch_bounds__(256) void k_map_backward(const float *__restrict__ 
         } else if (v >= xn) {
             if (grad_z) atomicAdd(&s_g[m - 1], (double)g);
         } else {
-            const int j = lut_segment(s_x, m, v);
+            const int j = lut_segment(s_x, top, m, v);
             const float dx = s_x[j + 1] - s_x[j];
             gi = g * __fdiv_rn(s_z[j + 1] - s_z[j], dx);
             if (grad_z) {
@@ -2161,7 +2179,7 @@ hipError_t launch_adam(float *x, const float *g, float *m, float *v, int64_t n, 
 hipError_t launch_map(const float *in, int64_t n, const LutArgs &lut, float *Z, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_map, dim3(grid_for(n, 256)), dim3(256), 0, st, in, (long long)n, lut, Z);
+    hipLaunchKernelGGL(k_map, dim3(grid_for((n + 3) / 4, 256)), dim3(256), 0, st, in, (long long)n, lut, Z);
     return hipGetLastError();
 }
 

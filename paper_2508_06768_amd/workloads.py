@@ -11,7 +11,10 @@
   adjoint, one launch sequence per pose against one graph-replayed step;
 * ``table_R_rays_S_samples``: single renders at the shapes of the paper's
   timing tables (Sec. 3.4, Tables 2-3: 64-256 rays, 32-200 samples, one
-  voxel per sample) on the 256^3 volume with speckle and blur.
+  voxel per sample) on the 256^3 volume with speckle and blur;
+* ``map_impedance_256cube``: the intensity -> impedance table over a 256^3
+  volume (12 knots) and its adjoint; bytes = 4 B read + 4 B written per
+  voxel forward, 8 B read + 4 B written adjoint.
 
 Prints one JSON line per workload: ms per call, ray-samples/s, and the
 algorithmic bytes as a share of the 8 TB/s HBM peak (forward: 4 B per
@@ -29,7 +32,7 @@ import numpy as np
 import torch
 
 from . import synth
-from .render import FusedStep, Geometry, footprint_voxels, render
+from .render import FusedStep, Geometry, footprint_voxels, map_impedance, map_impedance_backward, render
 
 HBM_PEAK = 8.0e12
 
@@ -112,6 +115,22 @@ def table_shapes(dev, reps=50):
             forward_only(case, dev, reps)
 
 
+def mapping(dev, reps=50):
+    n = 256 ** 3
+    rng = np.random.default_rng(1008)
+    xk = np.cumsum(rng.uniform(20.0, 200.0, 12)).astype(np.float32) - 500.0
+    zk = rng.uniform(1.3, 7.8, 12).astype(np.float32)
+    inten = torch.from_numpy(rng.uniform(float(xk[0]) - 50.0, float(xk[-1]) + 50.0, n).astype(np.float32)).to(dev)
+    Z = torch.empty_like(inten)
+    gZ = torch.from_numpy(rng.standard_normal(n).astype(np.float32)).to(dev)
+    for name, fn, nbytes in (("forward", lambda: map_impedance(inten, xk, zk, out=Z), 8 * n),
+                             ("adjoint", lambda: map_impedance_backward(inten, xk, zk, gZ), 12 * n)):
+        ms = _timed(fn, reps)
+        print(json.dumps({"workload": "map_impedance_256cube", "form": name, "ms": ms, "voxels": n,
+                          "voxels_per_s": n / (ms * 1e-3), "alg_bytes": nbytes,
+                          "hbm_frac": nbytes / (ms * 1e-3) / HBM_PEAK}), flush=True)
+
+
 def main(argv=None) -> None:
     import argparse
     ap = argparse.ArgumentParser()
@@ -125,6 +144,7 @@ def main(argv=None) -> None:
     case = synth.case_batched()
     fused(case, dev, per_pose=True)
     fused(case, dev, per_pose=False)
+    mapping(dev)
     if not args.skip_table:
         table_shapes(dev)
 
