@@ -365,3 +365,51 @@ def test_reconstruction_loop():
     assert res.loss_history[-1] < 0.85 * res.loss_history[0]
     assert bool(torch.isfinite(res.Z).all())
     assert float(res.Z.min()) >= 0.5 and float(res.Z.max()) <= 12.0
+
+
+def test_table_fit_gradient_through_the_renderer():
+    """End to end: intensity volume -> impedance table -> B-mode -> MSE.
+    dL/d(table values), chained through the GPU render adjoint and the map
+    adjoint, against central differences of the oracle's own pipeline
+    (oracle map, oracle render) in FP64."""
+    from scipy.ndimage import gaussian_filter
+
+    from paper_2508_06768_amd.render import Geometry, map_impedance, map_impedance_backward, render, render_backward
+    rng = np.random.default_rng(51)
+    n = 32
+    inten = gaussian_filter(rng.uniform(-120.0, 160.0, (n, n, n)), 1.5, mode="nearest")
+    inten[8:20, 10:22, 12:18] += 60.0                       # a block with sharp faces
+    inten = inten.astype(np.float32)
+    xk = np.array([-100.0, -40.0, 0.0, 30.0, 60.0, 120.0], dtype=np.float32)
+    zk = np.array([1.4, 1.5, 1.6, 1.7, 2.2, 3.0], dtype=np.float32)
+    fan = synth.FanSpec(16, 96, 50 * synth.DEG, 0.25, 0.0, 0)
+    phys = synth.PhysicsSpec(refl_mode=1)
+    pose = synth.top_pose(n)[None, :]
+
+    def oracle_image(z):
+        Z, _ = O.map_impedance(inten.astype(np.float64), xk.astype(np.float64), z)
+        return O.render(O.Volume(Z, (1.0,) * 3, (0.0,) * 3), pose[0].astype(np.float64), H.oracle_fan(fan),
+                        H.oracle_physics(phys)).reshape(-1)
+
+    def oracle_loss(z, T):
+        return float(np.mean((oracle_image(z) - T) ** 2))
+
+    T = oracle_image(zk.astype(np.float64) * np.array([1.0, 1.02, 0.97, 1.03, 1.0, 0.98]))
+    geom = Geometry((n, n, n), (1.0,) * 3, (0.0,) * 3, [fan], phys)
+    It = torch.from_numpy(inten).to(DEV)
+    Pt = torch.from_numpy(pose).to(DEV)
+    Z = map_impedance(It, xk, zk)
+    img = render(Z, Pt, geom)
+    g = (2.0 * (img.double() - torch.from_numpy(T).to(DEV)) / T.size).float()
+    gZ, _ = render_backward(Z, Pt, geom, g, want_pose=False)
+    _, gz = map_impedance_backward(It, xk, zk, gZ, want_intensity=False)
+    gz = gz.cpu().numpy()
+    h = 1e-5
+    fd = np.zeros(len(xk))
+    for j in range(len(xk)):
+        e = np.zeros(len(xk))
+        e[j] = h
+        fd[j] = (oracle_loss(zk.astype(np.float64) + e, T) - oracle_loss(zk.astype(np.float64) - e, T)) / (2 * h)
+    print("table gradient", gz, "fd", fd, flush=True)
+    assert np.linalg.norm(gz - fd) <= 1e-3 * np.linalg.norm(fd)
+
