@@ -212,6 +212,7 @@ struct WsLayout {
     size_t part = 0, part_bytes = 0;   // loss partials (plan step)
     size_t car = 0, car_bytes = 0;     // tile carries, 4 doubles per record (plan step)
     size_t cex = 0, cex_bytes = 0;     // tile-carry exponents, one int32 per record
+    size_t cst = 0, cst_bytes = 0;     // chunk states, kStateDoubles doubles per record
     size_t gain = 0, gain_bytes = 0;   // per-pixel gains recorded by the forward (plan step)
     size_t total = 0;
 };
@@ -263,6 +264,9 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         L.cex = off;
         L.cex_bytes = std::max<size_t>(rec, 1) * sizeof(int32_t);
         off = align_up(off + L.cex_bytes);
+        L.cst = off;
+        L.cst_bytes = std::max<size_t>(rec, 1) * dus::kStateDoubles * sizeof(double);
+        off = align_up(off + L.cst_bytes);
         if (p->speckle_on || p->atten_mode == DUS_ATTEN_POST_HOC) {
             L.gain = off;
             L.gain_bytes = img;
@@ -323,11 +327,11 @@ int make_sched(const dus_schedule *sc, Sched &n)
 int enqueue_forward(const Sched &sc, const dus::VolArgs &va, const dus::PhysArgs &pa,
                     const std::vector<dus::FanTable> &tabs, const float *poses, float *out,
                     float *min_pivot, hipStream_t st, double *carry = nullptr, int32_t *carry_exp = nullptr,
-                    float *gain = nullptr)
+                    double *cstate = nullptr, float *gain = nullptr)
 {
     for (const auto &t : tabs)
         DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, out, min_pivot, 0, carry,
-                                    carry_exp, gain, st),
+                                    carry_exp, cstate, gain, st),
                 "forward kernel launch");
     return DUS_OK;
 }
@@ -432,7 +436,7 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
         for (const auto &t : tabs)
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, src, nullptr,
                                          reinterpret_cast<float *>((char *)ws + L.zb), grad_Z,
-                                         grad_pose ? acc : nullptr, nullptr, nullptr, nullptr, nullptr, st),
+                                         grad_pose ? acc : nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st),
                     "adjoint kernel launch");
     }
     if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel launch");
@@ -714,10 +718,11 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     double *part = reinterpret_cast<double *>((char *)ws + p->ws.part);
     int64_t n_part = 0;
     const Sched &sc = p->sched;
-    // the forward records its tile carries and per-pixel gains; the adjoint
-    // starts from them
+    // the forward records its tile carries, chunk states and per-pixel
+    // gains; the adjoint starts from them
     double *car = reinterpret_cast<double *>((char *)ws + p->ws.car);
     int32_t *cex = reinterpret_cast<int32_t *>((char *)ws + p->ws.cex);
+    double *cst = reinterpret_cast<double *>((char *)ws + p->ws.cst);
     float *gain = p->ws.gain_bytes ? reinterpret_cast<float *>((char *)ws + p->ws.gain) : nullptr;
     const bool blur = p->phys.blur_on != 0;
     const bool fwd = blur || bmode;               // the forward kernel runs
@@ -729,7 +734,8 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     if (fwd) {
         int s;
         float *img = blur ? reinterpret_cast<float *>((char *)ws + p->ws.pre) : bmode;
-        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, img, nullptr, st, car, cex, gain)) != DUS_OK) return s;
+        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, img, nullptr, st, car, cex, cst, gain)) != DUS_OK)
+            return s;
     }
     DUS_HIP(mark(DUS_PHASE_BLUR_LOSS), "event");
     const float *eb = nullptr;
@@ -752,7 +758,8 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, blur ? nullptr : target, zbar,
                                         grad_pose ? acc : nullptr, (!blur && loss) ? part + n_part : nullptr,
-                                        fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? gain : nullptr, st),
+                                        fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? cst : nullptr,
+                                        fwd ? gain : nullptr, st),
                     "adjoint kernel");
             if (!blur) n_part += t.total_rays;
         }

@@ -34,6 +34,15 @@ inline int64_t carry_records(int32_t n_rays, int32_t n_samples)
     return (int64_t)n_rays * ((n_samples + kCarryBlock - 1) / kCarryBlock);
 }
 
+// Chunk states: the forward kernel also records (v0, v1, D) at every 4th
+// sample, in the frame of that sample's carry record, so that the adjoint
+// needs neither its own chunk products nor its prefix scan.  Each carry
+// record owns kStatesPerBlock states stored component-major (all v0, all v1,
+// all D): 3 * 64 doubles per record.
+constexpr int kStateStride = 4;
+constexpr int kStatesPerBlock = kCarryBlock / kStateStride;
+constexpr int kStateDoubles = 3 * kStatesPerBlock;
+
 struct FanTable {
     int32_t n;              // fans in this launch
     int32_t total_rays;
@@ -66,25 +75,27 @@ constexpr int kPoseAcc = 12;
 // Launch wrappers (kernels.hip).  All enqueue on `st` and return the HIP
 // error of the launch.
 // carry / carry_exp: optional tile-carry records (4 doubles / 1 int each);
+// cstate: optional chunk states (kStateDoubles per carry record; needs carry);
 // gain: optional per-pixel gain (speckle x post-hoc attenuation) output
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out,
                           float *min_pivot, int pivot_base, double *carry, int32_t *carry_exp,
-                          float *gain, hipStream_t st);
+                          double *cstate, float *gain, hipStream_t st);
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
 // the fused form (target given) loss receives one partial per ray
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
                            double *pose_acc, double *loss, const double *carry,
-                           const int32_t *carry_exp, const float *gain, hipStream_t st);
+                           const int32_t *carry_exp, const double *cstate, const float *gain,
+                           hipStream_t st);
 // the two halves of launch_backward: the adjoint scan (dL/dZ per sample into
 // zbar, pose sums, fused loss partials) and the scatter of zbar into gZ
 hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, const float *gsrc,
                           const float *target, float *zbar, double *pose_acc, double *loss,
-                          const double *carry, const int32_t *carry_exp, const float *gain,
-                          hipStream_t st);
+                          const double *carry, const int32_t *carry_exp, const double *cstate,
+                          const float *gain, hipStream_t st);
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
                           const float *poses, const float *zbar, float *gZ, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,

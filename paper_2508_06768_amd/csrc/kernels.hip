@@ -626,10 +626,12 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
                                                 float *__restrict__ out, float *__restrict__ minpiv,
                                                 int pivot_base, double *__restrict__ carry,
                                                 int32_t *__restrict__ carry_exp,
+                                                double *__restrict__ cstate,
                                                 float *__restrict__ gain_out, int xgrp)
 {
     constexpr int T = 64 * C;
     static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
+    static_assert(C % kStateStride == 0, "chunks hold whole state strides");
     constexpr int NB = T / kCarryBlock;     // carry blocks per tile
     constexpr int LB = kCarryBlock / C;     // lanes per carry block
     __shared__ double s_rho[T + T / 16];
@@ -654,7 +656,8 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     double c0 = 0.0, c1 = 1.0, cD = d_start(a2), zprev = 0.0;
     double piv = 1e300;
     const bool want_piv = (minpiv != nullptr);
-    const long long crec = (long long)fr.carry_begin + (long long)j * ((S + kCarryBlock - 1) / kCarryBlock);
+    const int nblk = (S + kCarryBlock - 1) / kCarryBlock;
+    const long long crec = (long long)fr.carry_begin + (long long)j * nblk;
     int first_rel = 0;      // exponent of this tile's carry relative to the previous record
 
     for (int t0 = 0; t0 < S; t0 += T) {
@@ -669,40 +672,45 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
         double qd, xd, td;
         chunk_product<C, false>(s_rho, base, t0, S, a2, sgn, Q, qd);
         scan_exclusive(lane, Q, qd, X, xd, Tot, td);
-        int e_last = 0;
+        double v0 = fma(c0, X.a, c1 * X.c);
+        double v1 = fma(c0, X.b, c1 * X.d);
+        double D = cD * xd;
         if (carry) {
             // state at the start of carry block m = lane / LB (lanes on a
-            // block boundary), renormalised; exponents relative to the
-            // previous block's
+            // block boundary), in the tile's frame: inside a tile the
+            // records share one scale, so only a tile's first record carries
+            // an exponent (relative to the previous record)
             const int m = lane / LB;
-            const double u0 = fma(c0, X.a, c1 * X.c);
-            const double u1 = fma(c0, X.b, c1 * X.d);
-            const double uD = cD * xd;
-            const int e = (lane == 0) ? 0 : renorm_exp(u0, u1);
-            const int e_prev = __shfl_up(e, LB);
             const int kb = t0 + m * kCarryBlock;
             if ((lane % LB) == 0 && kb < S) {
                 const long long r = crec + kb / kCarryBlock;
                 double *q = carry + 4 * r;
-                q[0] = (lane == 0) ? c0 : ldexp(u0, -e);
-                q[1] = (lane == 0) ? c1 : ldexp(u1, -e);
+                q[0] = v0;
+                q[1] = v1;
                 // the ray's first record in the adjoint's convention (identity
                 // map before sample 0): D = 1
-                q[2] = (lane == 0) ? (t0 == 0 ? 1.0 : cD) : ldexp(uD, -2 * e);
+                q[2] = (kb == 0) ? 1.0 : D;
                 q[3] = (m == 0) ? zstart : s_zc[m - 1];
-                carry_exp[r] = (m == 0) ? first_rel : e - e_prev;
+                carry_exp[r] = (m == 0) ? first_rel : 0;
             }
-            e_last = lane_read(e, LB * (NB - 1));
         }
-        double v0 = fma(c0, X.a, c1 * X.c);
-        double v1 = fma(c0, X.b, c1 * X.d);
-        double D = cD * xd;
+        // chunk states for the adjoint: the lane's C samples lie in one
+        // carry block (the ray's first state is taken in the adjoint's
+        // convention by the adjoint itself)
+        double *qs = nullptr;
+        if (cstate && (t0 + base) / kCarryBlock < nblk)
+            qs = cstate + (crec + (t0 + base) / kCarryBlock) * kStateDoubles + ((t0 + base) % kCarryBlock) / kStateStride;
         float pix[C];
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             // branch-free: outside [1, S) rho = 0, so the pixel is 0 and v1
             // unchanged (make_map)
             const int k = t0 + base + i;
+            if ((i % kStateStride) == 0 && qs) {
+                qs[i / kStateStride] = v0;
+                qs[kStatesPerBlock + i / kStateStride] = v1;
+                qs[2 * kStatesPerBlock + i / kStateStride] = D;
+            }
             const double r = s_rho[pad8(base + i)];
             const Map m = make_map(r, a2, sgn);
             const double v1n = fma(v0, r, v1);
@@ -722,7 +730,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             c0 = ldexp(n0, -ex);
             c1 = ldexp(n1, -ex);
             cD = ldexp(nD, -2 * ex);
-            first_rel = ex - e_last;
+            first_rel = ex;
         }
         // per-pixel gains and the stores, in the lane's chunk order (the
         // lane's C samples start at a multiple of 4: its granular variates
@@ -831,6 +839,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                                                  double *__restrict__ loss_acc,
                                                  const double *__restrict__ carry,
                                                  const int32_t *__restrict__ carry_exp,
+                                                 const double *__restrict__ cstate,
                                                  const float *__restrict__ gain_in, int xgrp)
 {
     constexpr int T = 64 * C;
@@ -868,12 +877,12 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     const int ntiles = (S + T - 1) / T;
     const double inv_npix = 1.0 / ((double)fr.n_rays * (double)S);
 
+    const int nblk = (S + kCarryBlock - 1) / kCarryBlock;
+    const long long rb = (long long)fr.carry_begin + (long long)j * nblk;
+    __shared__ int s_bexp[(DUS_MAX_SAMPLES + kCarryBlock - 1) / kCarryBlock];
     if (carry) {
         // tile starts from the forward kernel's carry records; the exponent
         // of tile t relative to tile t - 1 sums those of its carry blocks
-        __shared__ int s_bexp[(DUS_MAX_SAMPLES + kCarryBlock - 1) / kCarryBlock];
-        const int nblk = (S + kCarryBlock - 1) / kCarryBlock;
-        const long long rb = (long long)fr.carry_begin + (long long)j * nblk;
         for (int b = lane; b < nblk; b += 64) {
             s_bexp[b] = carry_exp[rb + b];
             if (b % NB == 0) {
@@ -885,11 +894,32 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             }
         }
         __syncthreads();
-        for (int t = 1 + lane; t < ntiles; t += 64) {
-            int e = 0;
+        // A tile's frame is its first record renormalised by a power of two
+        // (the forward's records share one scale inside a forward tile).
+        // Lane t takes tile t (ntiles <= 64): s_cexp[t] becomes the exponent
+        // of tile t's frame relative to tile t - 1's, and s_bexp[b] that of
+        // block b's record relative to its tile's frame.
+        const int t = lane;
+        int et = 0, cex = 0, rel[NB];
+        if (t < ntiles) {
+            et = renorm_exp(s_carry[t][0], s_carry[t][1]);
+            if (t > 0) {
+                cex = et - renorm_exp(s_carry[t - 1][0], s_carry[t - 1][1]);
 #pragma unroll
-            for (int q = 0; q < NB; ++q) e += s_bexp[(t - 1) * NB + 1 + q];
-            s_cexp[t] = e;
+                for (int q = 0; q < NB; ++q) cex += s_bexp[(t - 1) * NB + 1 + q];
+            }
+            rel[0] = -et;
+#pragma unroll
+            for (int u = 1; u < NB; ++u) rel[u] = rel[u - 1] + s_bexp[t * NB + u];
+        }
+        __syncthreads();
+        if (t < ntiles) {
+            s_carry[t][0] = ldexp(s_carry[t][0], -et);
+            s_carry[t][1] = ldexp(s_carry[t][1], -et);
+            s_carry[t][2] = ldexp(s_carry[t][2], -2 * et);
+            s_cexp[t] = cex;
+#pragma unroll
+            for (int u = 0; u < NB; ++u) s_bexp[t * NB + u] = rel[u];
         }
     } else {
         // forward sweep: state at every tile start
@@ -930,9 +960,22 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
     for (int t = ntiles - 1; t >= 0; --t) {
         const int t0 = t * T;
-        const double c0 = s_carry[t][0], c1 = s_carry[t][1], cD = s_carry[t][2];
         const double zstart = s_carry[t][3];
         double zprev = zstart;
+        const int base = lane * C;
+        // the state at the lane's chunk start, from the forward's chunk
+        // states when it recorded them (loads issued before the gather)
+        double v0s = 0.0, v1s = 1.0, Ds = 1.0;
+        if (cstate) {
+            const int k = t0 + base;
+            if (k / kCarryBlock < nblk) {
+                const double *q = cstate + (rb + k / kCarryBlock) * kStateDoubles + (k % kCarryBlock) / kStateStride;
+                v0s = q[0];
+                v1s = q[kStatesPerBlock];
+                // the ray's first state in the adjoint's convention: D = 1
+                Ds = (k == 0) ? 1.0 : q[2 * kStatesPerBlock];
+            }
+        }
         if (pose_acc)
             gather_tile<C, true, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, nullptr, s_dq);
         else
@@ -942,27 +985,37 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         // dL/de (or the target for the fused loss) staged through LDS: the C
         // global loads are issued together, then the per-pixel gains
         // (speckle, post-hoc attenuation) are applied in place
+        // the loads are clamped into the ray and issued together (no
+        // per-load branches, one wait); samples past the ray read as zero
+        const float *src = FUSED ? target : gsrc;
         if (gain_in) {
             // gains recorded by the forward kernel
+            float x[C], gn[C];
+#pragma unroll
+            for (int m = 0; m < C; ++m) {
+                const int k = min(t0 + m * 64 + lane, S - 1);
+                x[m] = src[obase + k];
+                gn[m] = gain_in[obase + k];
+            }
 #pragma unroll
             for (int m = 0; m < C; ++m) {
                 const int i = m * 64 + lane;
-                const int k = t0 + i;
-                const float x = (k < S) ? (FUSED ? target[obase + k] : gsrc[obase + k]) : 0.0f;
-                const float gn = (k < S) ? gain_in[obase + k] : 1.0f;
+                const bool in = (t0 + i < S);
                 if (FUSED) {
-                    s_eb[pad4(i)] = x;
-                    s_gain[pad4(i)] = gn;
+                    s_eb[pad4(i)] = in ? x[m] : 0.0f;
+                    s_gain[pad4(i)] = in ? gn[m] : 1.0f;
                 } else {
-                    s_eb[pad4(i)] = x * gn;
+                    s_eb[pad4(i)] = in ? x[m] * gn[m] : 0.0f;
                 }
             }
         } else {
+            float x[C];
+#pragma unroll
+            for (int m = 0; m < C; ++m) x[m] = src[obase + min(t0 + m * 64 + lane, S - 1)];
 #pragma unroll
             for (int m = 0; m < C; ++m) {
                 const int i = m * 64 + lane;
-                const int k = t0 + i;
-                s_eb[pad4(i)] = (k < S) ? (FUSED ? target[obase + k] : gsrc[obase + k]) : 0.0f;
+                s_eb[pad4(i)] = (t0 + i < S) ? x[m] : 0.0f;
             }
             const bool has_gain = SPK || p.atten == 1;
 #pragma unroll 1
@@ -976,24 +1029,39 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         }
         __syncthreads();
 
-        const int base = lane * C;
-        Mat Q, X, Tot;
-        double qd, xd, td;
-        chunk_product<C, true>(s_rho, base, t0, S, a2, sgn, Q, qd);
-        scan_exclusive(lane, Q, qd, X, xd, Tot, td);
+        if (cstate) {
+            // from the frame of the state's block record to the tile's frame
+            // (the exponent is read here, after the barrier, so that the
+            // scaling, and the wait for the loads above, stay behind the gather)
+            const int es = s_bexp[min((t0 + base) / kCarryBlock, nblk - 1)];
+            v0s = ldexp(v0s, es);
+            v1s = ldexp(v1s, es);
+            Ds = ldexp(Ds, 2 * es);
+        } else {
+            // otherwise from the tile's carry and a prefix scan of the
+            // lanes' chunk products
+            Mat Q, X, Tot;
+            double qd, xd, td;
+            chunk_product<C, true>(s_rho, base, t0, S, a2, sgn, Q, qd);
+            scan_exclusive(lane, Q, qd, X, xd, Tot, td);
+            const double c0 = s_carry[t][0], c1 = s_carry[t][1], cD = s_carry[t][2];
+            v0s = fma(c0, X.a, c1 * X.c);
+            v1s = fma(c0, X.b, c1 * X.d);
+            Ds = cD * xd;
+        }
         // Walk 1 (forward over the lane's C interfaces): the chunk's affine
         // adjoint map lambda_start = lambda_end J_chunk + f_chunk, with
         // J_chunk = diag(Q^T, det) and f_chunk = sum_i f_i (Q_i^loc)^T, where
         // Q_i^loc = M_first .. M_{i-1} and f_i is step i's forcing (adj_forcing).
-        const double v0s = fma(c0, X.a, c1 * X.c);
-        const double v1s = fma(c0, X.b, c1 * X.d);
-        const double Ds = cD * xd;
+        // The walk's final Q^loc is the chunk product Q itself.
         Adj f{0.0, 0.0, 0.0};
+        Mat Q{1.0, 0.0, 0.0, 1.0};
+        double qd = 1.0;
         const double w1s = rcp64(v1s);     // 1 / v1 at the chunk start
         {
             double v0 = v0s, v1 = v1s, D = Ds, w1 = w1s;
-            Mat QL{1.0, 0.0, 0.0, 1.0};
-            double qdl = 1.0;
+            Mat &QL = Q;
+            double &qdl = qd;
             // branch-free: an interface outside [1, S) has rho = 0 (gather)
             // and the identity map, so its step leaves the state unchanged and
             // forces nothing (pixel 0 is zero; the loss still counts it)
@@ -1482,20 +1550,25 @@ __global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const fl
     const float two_inv_npix = (float)(2.0 * inv_npix);
     double lsum = 0.0;
     if (active) {
+        // every load clamped into the fan (no per-load branches): MODE 1
+        // then zeroes the rows outside it, the others replicate the edge
         float x[W];
 #pragma unroll
         for (int m = 0; m < W; ++m) {
             const int g = j0 - RM + m;
-            if (MODE == 1)
-                x[m] = (g >= 0 && g < n) ? in[col + (long long)g * S] : 0.0f;
-            else
-                x[m] = in[col + (long long)min(max(g, 0), n - 1) * S];
+            x[m] = in[col + (long long)min(max(g, 0), n - 1) * S];
         }
         float tg[MODE == 2 ? kBlurRows : 1];
         if (MODE == 2) {
 #pragma unroll
-            for (int o = 0; o < kBlurRows; ++o)
-                tg[o] = (j0 + o < n) ? target[col + (long long)(j0 + o) * S] : 0.0f;
+            for (int o = 0; o < kBlurRows; ++o) tg[o] = target[col + (long long)min(j0 + o, n - 1) * S];
+        }
+        if (MODE == 1) {
+#pragma unroll
+            for (int m = 0; m < W; ++m) {
+                const int g = j0 - RM + m;
+                x[m] = (g >= 0 && g < n) ? x[m] : 0.0f;
+            }
         }
         float w[RM + 1];
         const int r = blur_weights<RM>(p, S, k, w);
@@ -1751,15 +1824,20 @@ __global__ __launch_bounds__(256) void k_smooth(const float *__restrict__ Z, int
         const long long r = v / nx;
         const int iy = (int)(r % ny), iz = (int)(r / ny);
         const long long sxy = (long long)nx * ny;
+        // neighbours clamped to the voxel itself at the faces, where their
+        // differences are then exactly zero: the seven loads issue together
         const float z = Z[v];
+        const float xm = Z[v - (ix > 0 ? 1 : 0)], xp = Z[v + (ix + 1 < nx ? 1 : 0)];
+        const float ym = Z[v - (iy > 0 ? nx : 0)], yp = Z[v + (iy + 1 < ny ? nx : 0)];
+        const float zm = Z[v - (iz > 0 ? sxy : 0)], zp = Z[v + (iz + 1 < nz ? sxy : 0)];
         float g = 0.0f;
         // axis weights w / h^2; d(Z_b - Z_a)^2 / dZ = -2 (Z_b - Z_a) for a, +2 for b
-        if (ix > 0) g += 2.0f * wx * (z - Z[v - 1]);
-        if (ix + 1 < nx) { const float d = Z[v + 1] - z; g -= 2.0f * wx * d; e += (double)wx * (double)d * (double)d; }
-        if (iy > 0) g += 2.0f * wy * (z - Z[v - nx]);
-        if (iy + 1 < ny) { const float d = Z[v + nx] - z; g -= 2.0f * wy * d; e += (double)wy * (double)d * (double)d; }
-        if (iz > 0) g += 2.0f * wz * (z - Z[v - sxy]);
-        if (iz + 1 < nz) { const float d = Z[v + sxy] - z; g -= 2.0f * wz * d; e += (double)wz * (double)d * (double)d; }
+        g += 2.0f * wx * (z - xm);
+        { const float d = xp - z; g -= 2.0f * wx * d; e += (double)wx * (double)d * (double)d; }
+        g += 2.0f * wy * (z - ym);
+        { const float d = yp - z; g -= 2.0f * wy * d; e += (double)wy * (double)d * (double)d; }
+        g += 2.0f * wz * (z - zm);
+        { const float d = zp - z; g -= 2.0f * wz * d; e += (double)wz * (double)d * (double)d; }
         gZ[v] += g;
     }
     __shared__ double s_w[4];
@@ -1948,17 +2026,20 @@ inline int grid_for(long long n, int block)
     case CH:                                                                                   \
         if (p.speckle)                                                                         \
             hipLaunchKernelGGL((k_forward<CH, true>), dim3(grid), dim3(64), 0, st, v, p, t,    \
-                               poses, out, min_pivot, pivot_base, carry, carry_exp, gain,      \
+                               poses, out, min_pivot, pivot_base, carry, carry_exp, cstate,    \
+                               gain,                                                           \
                                xcd_group);                                                     \
         else                                                                                   \
             hipLaunchKernelGGL((k_forward<CH, false>), dim3(grid), dim3(64), 0, st, v, p, t,   \
-                               poses, out, min_pivot, pivot_base, carry, carry_exp, gain,      \
+                               poses, out, min_pivot, pivot_base, carry, carry_exp, cstate,    \
+                               gain,                                                           \
                                xcd_group);                                                     \
         break;
 
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out, float *min_pivot,
-                          int pivot_base, double *carry, int32_t *carry_exp, float *gain, hipStream_t st)
+                          int pivot_base, double *carry, int32_t *carry_exp, double *cstate, float *gain,
+                          hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
@@ -1974,7 +2055,8 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 #define DUS_BWD_LAUNCH(CH, SPK, FUSED)                                                          \
     hipLaunchKernelGGL((k_backward<CH, SPK, FUSED>), dim3(grid), dim3(64), 0, st, v, p, t,      \
-                       poses, gsrc, target, zbar, pose_acc, loss, carry, carry_exp, gain, xcd_group)
+                       poses, gsrc, target, zbar, pose_acc, loss, carry, carry_exp, cstate, gain,        \
+                       xcd_group)
 
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
@@ -1990,13 +2072,14 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, const float *gsrc,
                           const float *target, float *zbar, double *pose_acc, double *loss,
-                          const double *carry, const int32_t *carry_exp, const float *gain,
-                          hipStream_t st)
+                          const double *carry, const int32_t *carry_exp, const double *cstate,
+                          const float *gain, hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
     const bool fused = (target != nullptr);
     const bool spk = p.speckle && !gain;      // recorded gains replace the speckle variates
+    if (!carry) cstate = nullptr;             // chunk states are read in the frames of the carry records
     switch (chunk) {
         DUS_BWD_CASE(4)
         DUS_BWD_CASE(8)
@@ -2047,10 +2130,11 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
                            double *pose_acc, double *loss, const double *carry,
-                           const int32_t *carry_exp, const float *gain, hipStream_t st)
+                           const int32_t *carry_exp, const double *cstate, const float *gain,
+                           hipStream_t st)
 {
     hipError_t e = launch_adjoint(chunk, xcd_group, v, p, t, poses, gsrc, target, zbar, pose_acc, loss, carry,
-                                  carry_exp, gain, st);
+                                  carry_exp, cstate, gain, st);
     if (e != hipSuccess) return e;
     return launch_scatter(scatter_rays, xcd_group, v, t, poses, zbar, gZ, st);
 }

@@ -10,6 +10,7 @@ Bars:
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_2508_06768_amd import synth
 from tests import helpers as H
 
@@ -142,43 +143,108 @@ def test_backward_parity_ragged(refl, effects):
         assert np.all(np.abs(gp[p] - rp[p]) <= RTOL_GRAD * nrm + 1e-30)
 
 
+def _plan_reference(case, target):
+    """Oracle image, MSE loss (mean per fan, summed over fans), dL/dZ and
+    dL/dpose of the fused step."""
+    img = H.oracle_render(case)
+    tf = target.astype(np.float32).astype(np.float64)
+    ref_loss = 0.0
+    grad = np.zeros_like(img)
+    off = 0
+    for f in case.fans:
+        n = f.n_rays * f.n_samples
+        d = img[off:off + n] - tf[off:off + n]
+        ref_loss += np.mean(d * d)
+        grad[off:off + n] = 2 * d / n
+        off += n
+    rV, rp = H.oracle_backward(case, grad)
+    return img, ref_loss, rV, rp
+
+
+def _run_plan(case, target, schedule=None, replays=3):
+    from paper_2508_06768_amd.render import FusedStep
+    geom, Z, poses = _gpu(case)
+    T = torch.from_numpy(target.astype(np.float32)).to(DEV)
+    step = FusedStep(geom, zero_grad_z=True, schedule=schedule)
+    bm = torch.empty(geom.total, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    gZ = torch.full_like(Z, 123.0)
+    gp = torch.empty((geom.n_poses, 6), device=DEV)
+    for _ in range(replays):                    # replays of the same graph
+        step.step(Z, poses, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+    torch.cuda.synchronize()
+    out = (bm.cpu().numpy(), loss.item(), gZ.cpu().numpy(), gp.cpu().numpy())
+    step.close()
+    return out
+
+
+def _check_plan(case, got, ref, tag):
+    bm, loss, gZ, gp = got
+    img, ref_loss, rV, rp = ref
+    _check_images(bm, img, f"{tag} image", case.fans)
+    assert loss == pytest.approx(ref_loss, rel=1e-5)
+    e = H.rel_l2(gZ, rV)
+    print(tag, "dZ rel l2", e, flush=True)
+    assert e <= RTOL_GRAD
+    for p in range(len(case.fans)):
+        assert np.all(np.abs(gp[p] - rp[p]) <= RTOL_GRAD * np.linalg.norm(rp[p]) + 1e-30)
+
+
 def test_fused_plan_matches_oracle():
     """dus_plan step (forward + MSE + adjoint in one captured graph)."""
-    from paper_2508_06768_amd.render import FusedStep
     for effects in (False, True):
         case = ragged_case(0, 0, effects, seed=21)
-        geom, Z, poses = _gpu(case)
         tgt_poses = case.poses + np.float32([[0.6, -0.3, 0.2, 0.02, -0.03, 0.05]])
         target = H.oracle_render(case, poses=tgt_poses)
-        T = torch.from_numpy(target.astype(np.float32)).to(DEV)
-        step = FusedStep(geom, zero_grad_z=True)
-        bm = torch.empty(geom.total, device=DEV)
-        loss = torch.zeros(1, dtype=torch.float64, device=DEV)
-        gZ = torch.full_like(Z, 123.0)
-        gp = torch.empty((geom.n_poses, 6), device=DEV)
-        for _ in range(3):                      # replays of the same graph
-            step.step(Z, poses, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
-        torch.cuda.synchronize()
-        img = H.oracle_render(case)
-        tf = target.astype(np.float32).astype(np.float64)
-        ref_loss = 0.0
-        grad = np.zeros_like(img)
-        off = 0
-        for f in case.fans:
-            n = f.n_rays * f.n_samples
-            d = img[off:off + n] - tf[off:off + n]
-            ref_loss += np.mean(d * d)
-            grad[off:off + n] = 2 * d / n
-            off += n
-        rV, rp = H.oracle_backward(case, grad)
-        _check_images(bm.cpu().numpy(), img, f"plan image fx={effects}", case.fans)
-        assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
-        e = H.rel_l2(gZ.cpu().numpy(), rV)
-        print("plan dZ rel l2", e, flush=True)
-        assert e <= RTOL_GRAD
-        gpn = gp.cpu().numpy()
-        for p in range(len(case.fans)):
-            assert np.all(np.abs(gpn[p] - rp[p]) <= RTOL_GRAD * np.linalg.norm(rp[p]) + 1e-30)
+        _check_plan(case, _run_plan(case, target), _plan_reference(case, target), f"plan fx={effects}")
+
+
+def rough_column_case(refl, effects, seed=13) -> synth.Case:
+    """A 1100 x 8 x 8 column of independent uniform voxels crossed one voxel
+    per sample (U(1.4, 1.8) in the |R| convention, U(1, 3) signed): every
+    interface reflects, and with the attenuation the largest entry of the
+    carried row vector drops through several powers of two along a ray, so
+    the forward's carry records and chunk states hold exponents that the
+    adjoint must undo.  All pivots stay above 0.9.  Fans of 1000 and 777
+    samples."""
+    rng = np.random.default_rng(seed)
+    lo, hi = (1.4, 1.8) if refl == 0 else (1.0, 3.0)
+    Z = rng.uniform(lo, hi, size=(1100, 8, 8)).astype(np.float32)
+    poses = np.array([[3.5, 3.5, 0.0, 0.0, 0.0, 0.0],
+                      [3.2, 3.9, 1.0, 0.002, -0.003, 0.1]], dtype=np.float32)
+    fans = [synth.FanSpec(3, 1000, 0.02, 1.0, 0.5, 0), synth.FanSpec(2, 777, 0.01, 1.0, 0.2, 1)]
+    ph = synth.PhysicsSpec(refl_mode=refl, speckle_on=effects, blur_on=effects, seed=seed)
+    return synth.Case("column", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans, ph)
+
+
+@pytest.mark.parametrize("refl,effects", [(0, False), (1, True)])
+def test_plan_schedules_with_renormalised_carries(refl, effects):
+    """The forward hands the adjoint its tile carries and chunk states in
+    the frames of its own tiles.  Every pairing of forward tile (4, 8, 16
+    samples per lane) and adjoint tile (4, 8) must give the oracle's image,
+    loss and gradients on rays whose carried vector is renormalised."""
+    case = rough_column_case(refl, effects)
+    # premise: the power of two of the carried vector changes from one
+    # 256-sample block to the next (products of the Eq. 2-4 transfer maps
+    # over the oracle's samples of the first ray)
+    Zs = O.ray_samples(H.oracle_volume(case), case.poses[0].astype(np.float64), H.oracle_fan(case.fans[0]), 1)
+    a2 = O.step_amplitude(H.oracle_physics(case.phys), case.fans[0].ds) ** 2
+    sgn = 1.0 if refl == 0 else -1.0
+    v = np.array([0.0, 1.0])
+    ex = []
+    for i in range(1, len(Zs)):
+        r = O.coeffs(Zs[i - 1], Zs[i], refl)[0]
+        v = v @ np.array([[a2 * (1.0 - r * r - sgn * r * r), r], [-a2 * sgn * r, 1.0]])
+        if (i + 1) % 256 == 0:
+            ex.append(int(np.floor(np.log2(np.abs(v).max()))))
+    assert len(set(ex)) >= 2 and min(ex) < 0, ex
+    tgt_poses = case.poses + np.float32([[0.1, -0.1, 0.0, 0.0, 0.0, 0.0]])
+    target = H.oracle_render(case, poses=tgt_poses)
+    ref = _plan_reference(case, target)
+    for fc in (4, 8, 16):
+        for bc in (4, 8):
+            sched = {"fwd_chunk": fc, "bwd_chunk": bc, "xcd_group": 1, "scatter_rays": 2}
+            _check_plan(case, _run_plan(case, target, sched, replays=2), ref, f"column fwd {fc} bwd {bc}")
 
 
 # --------------------------------------------------------------------------
