@@ -727,9 +727,12 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     const bool blur = p->phys.blur_on != 0;
     const bool fwd = blur || bmode;               // the forward kernel runs
     DUS_HIP(mark(DUS_PHASE_CLEAR), "event");
-    if (grad_pose) DUS_HIP(dus::launch_zero_f64(acc, (int64_t)n_poses * dus::kPoseAcc, st), "zero kernel");
-    if (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z))
-        DUS_HIP(dus::launch_zero_f32(gZ, (int64_t)p->vol.nx * p->vol.ny * p->vol.nz, st), "zero kernel");
+    {
+        // the pose accumulators and dL/dZ cleared in one launch
+        const int64_t na = (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z)) ? (int64_t)p->vol.nx * p->vol.ny * p->vol.nz : 0;
+        const int64_t nb = grad_pose ? (int64_t)n_poses * dus::kPoseAcc : 0;
+        DUS_HIP(dus::launch_zero_pair(gZ, na, acc, nb, st), "zero kernel");
+    }
     DUS_HIP(mark(DUS_PHASE_FORWARD), "event");
     if (fwd) {
         int s;
@@ -768,8 +771,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         for (const auto &t : p->tabs)
             DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, poses, zbar, gZ, st), "scatter kernel");
     DUS_HIP(mark(DUS_PHASE_FINISH), "event");
-    if (loss) DUS_HIP(dus::launch_sum_f64(part, n_part, loss, st), "loss sum kernel");
-    if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel");
+    DUS_HIP(dus::launch_finish(part, n_part, loss, acc, poses, n_poses, grad_pose, st), "loss and pose kernel");
     DUS_HIP(mark(DUS_NUM_PHASES), "event");
     return DUS_OK;
 }

@@ -121,6 +121,12 @@ hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t st);
 // *out = sum of the n partials (the loss of the fused step)
 hipError_t launch_sum_f64(const double *part, int64_t n, double *out, hipStream_t st, bool accumulate = false);
+// loss = sum of the partials (if loss) and grad = the finalised pose
+// gradients (if grad), in one launch
+hipError_t launch_finish(const double *part, int64_t n_part, double *loss, const double *acc, const float *poses,
+                         int n_poses, float *grad, hipStream_t st);
+// a[0..na) = 0 and b[0..nb) = 0 in one launch
+hipError_t launch_zero_pair(float *a, int64_t na, double *b, int64_t nb, hipStream_t st);
 // smoothness prior of the reconstruction: per-axis weights w / h^2; one
 // energy partial per block of 256 voxels (smooth_blocks of them)
 int64_t smooth_blocks(int nx, int ny, int nz);

@@ -94,7 +94,7 @@ __device__ __forceinline__ double div64(double a, double b)
 // partial unroll of the sample-gather loops: enough independent gathers in
 // flight without holding every tile sample in registers
 #ifndef GATHER_UNROLL
-#define GATHER_UNROLL 2
+#define GATHER_UNROLL 4
 #endif
 
 // LDS index padding: doubles (one pad word per 16) and floats (per 32)
@@ -1638,11 +1638,10 @@ __device__ void mm3(const double *A, const double *B, double *Cm)
             Cm[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
 }
 
-__global__ void k_pose_finalize(const double *__restrict__ acc, const float *__restrict__ poses,
-                                int n, float *__restrict__ grad)
+// pose pi's (dL/dt, dL/dw) from its accumulator
+__device__ void pose_finalize_one(const double *__restrict__ acc, const float *__restrict__ poses, int pi,
+                                  float *__restrict__ grad)
 {
-    const int pi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pi >= n) return;
     const double *a = acc + (size_t)kPoseAcc * pi;
     const double w[3] = {poses[6 * pi + 3], poses[6 * pi + 4], poses[6 * pi + 5]};
     const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
@@ -1676,6 +1675,13 @@ __global__ void k_pose_finalize(const double *__restrict__ acc, const float *__r
         grad[6 * pi + 3 + c] = (float)s;
     }
     for (int q = 0; q < 3; ++q) grad[6 * pi + q] = (float)a[q];
+}
+
+__global__ void k_pose_finalize(const double *__restrict__ acc, const float *__restrict__ poses,
+                                int n, float *__restrict__ grad)
+{
+    const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pi < n) pose_finalize_one(acc, poses, pi, grad);
 }
 
 // --------------------------------------------------------------------------
@@ -1790,8 +1796,8 @@ __global__ void k_zero_f32(float *p, long long n)
 
 // out = sum of n partials, or out += it (single block, fixed order:
 // deterministic)
-__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, long long n, double *__restrict__ out,
-                                                 int accumulate)
+__device__ __forceinline__ void sum_block(const double *__restrict__ part, long long n, double *__restrict__ out,
+                                          int accumulate)
 {
     __shared__ double s_w[4];
     double acc = 0.0;
@@ -1803,6 +1809,43 @@ __global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part
         const double t = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
         *out = accumulate ? *out + t : t;
     }
+}
+
+__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ part, long long n, double *__restrict__ out,
+                                                 int accumulate)
+{
+    sum_block(part, n, out, accumulate);
+}
+
+// the end of a fused step in one launch: block 0 sums the loss partials
+// (when loss is given), the other blocks finalise 256 poses each
+__global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part, long long n_part,
+                                                double *__restrict__ loss, const double *__restrict__ acc,
+                                                const float *__restrict__ poses, int n_poses,
+                                                float *__restrict__ grad)
+{
+    if (loss && blockIdx.x == 0) {
+        sum_block(part, n_part, loss, 0);
+        return;
+    }
+    const int pi = (blockIdx.x - (loss ? 1 : 0)) * 256 + threadIdx.x;
+    if (grad && pi < n_poses) pose_finalize_one(acc, poses, pi, grad);
+}
+
+// two buffers cleared in one launch (grid-stride over both)
+__global__ void k_zero_pair(float *__restrict__ a, long long na, double *__restrict__ b, long long nb)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long n4 = na / 4;
+    float4 *a4 = reinterpret_cast<float4 *>(a);
+    if ((reinterpret_cast<uintptr_t>(a) & 15) == 0) {
+        for (long long i = i0; i < n4; i += stride) a4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (long long i = 4 * n4 + i0; i < na; i += stride) a[i] = 0.0f;
+    } else {
+        for (long long i = i0; i < na; i += stride) a[i] = 0.0f;
+    }
+    for (long long i = i0; i < nb; i += stride) b[i] = 0.0;
 }
 
 // --------------------------------------------------------------------------
@@ -2231,6 +2274,25 @@ hipError_t launch_zero_f32(float *ptr, int64_t n, hipStream_t st)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_f32, dim3(grid_for((n + 3) / 4, 256)), dim3(256), 0, st, ptr,
                        (long long)n);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const double *part, int64_t n_part, double *loss, const double *acc, const float *poses,
+                         int n_poses, float *grad, hipStream_t st)
+{
+    const int pose_blocks = grad ? (n_poses + 255) / 256 : 0;
+    const int grid = (loss ? 1 : 0) + pose_blocks;
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finish, dim3(grid), dim3(256), 0, st, part, (long long)n_part, loss, acc, poses, n_poses,
+                       grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_pair(float *a, int64_t na, double *b, int64_t nb, hipStream_t st)
+{
+    if (na <= 0 && nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_pair, dim3(grid_for(std::max<int64_t>((na + 3) / 4, nb), 256)), dim3(256), 0, st, a,
+                       (long long)na, b, (long long)nb);
     return hipGetLastError();
 }
 
