@@ -458,6 +458,12 @@ __device__ __forceinline__ void gather_tile_body(const VolArgs &v, const Ray &ra
 {
     constexpr int T = 64 * C;
     const int sxy = v.nx * v.ny;
+    // 1 / h once per tile, not an FP64 division per sample and axis
+    double ih[3] = {0.0, 0.0, 0.0};
+    if (KEEPG) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ih[a] = 1.0 / (double)v.h[a];
+    }
 #pragma unroll GATHER_UNROLL
     for (int jj = 0; jj < C; ++jj) {
         const int i = jj * 64 + lane;
@@ -489,7 +495,7 @@ __device__ __forceinline__ void gather_tile_body(const VolArgs &v, const Ray &ra
             for (int a = 0; a < 3; ++a) {
                 const double u = fma(kk, ray.du[a], ray.u0[a]);
                 const bool inside = INSIDE || ((u >= 0.0) && (u <= (double)(n[a] - 1)));
-                s_g[a * T + i] = inside ? (float)(gu[a] / (double)v.h[a]) : 0.0f;
+                s_g[a * T + i] = inside ? (float)(gu[a] * ih[a]) : 0.0f;
             }
         }
     }
