@@ -25,8 +25,10 @@ static_assert(sizeof(FanRec) == 56, "FanRec layout");
 
 // Tile carries: the forward kernel records, at every 256-sample boundary of
 // a ray, the carried row vector and determinant (v0, v1, D) and the sample
-// before the boundary, renormalised by a power of two whose exponent is
-// stored relative to the previous boundary.  The adjoint then starts its
+// before the boundary, in the scale of the forward tile that holds the
+// boundary.  Each record's exponent gives that scale relative to the
+// previous record's: zero inside a forward tile, the tile's renormalisation
+// (a power of two) at its first record.  The adjoint then starts its
 // reverse sweep from these records instead of re-running the forward.
 constexpr int kCarryBlock = 256;
 inline int64_t carry_records(int32_t n_rays, int32_t n_samples)
