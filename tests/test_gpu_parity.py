@@ -153,6 +153,8 @@ def _plan_reference(case, target):
     off = 0
     for f in case.fans:
         n = f.n_rays * f.n_samples
+        if n == 0:
+            continue                            # an empty fan adds nothing
         d = img[off:off + n] - tf[off:off + n]
         ref_loss += np.mean(d * d)
         grad[off:off + n] = 2 * d / n

@@ -254,8 +254,10 @@ def test_binding_rejects_short_buffers():
 
 def test_edge_sizes():
     """Maximum samples per ray, single ray, one and two samples, an empty fan,
-    and a volume with 2-voxel axes."""
+    and a volume with 2-voxel axes: render and adjoint, and the fused step
+    (whose adjoint starts from the forward's carries and chunk states)."""
     from paper_2508_06768_amd.render import render, render_backward
+    from tests.test_gpu_parity import _check_plan, _plan_reference, _run_plan
     Z = synth.brain_volume(9, 32, 1.0, semi_range=(2.0, 8.0))
     Z2 = np.ascontiguousarray(Z[:2, :2, :])                      # nz = ny = 2
     for Zv, fans, poses in [
@@ -284,6 +286,8 @@ def test_edge_sizes():
             assert H.rel_l2(gZ.cpu().numpy(), rV) <= 1e-5
         for p in range(len(fans)):
             assert np.all(np.abs(gp.cpu().numpy()[p] - rp[p]) <= 1e-5 * np.linalg.norm(rp[p]) + 1e-30)
+        target = H.oracle_render(case, poses=case.poses + np.float32([[0.3, -0.2, 0.1, 0.0, 0.0, 0.0]]))
+        _check_plan(case, _run_plan(case, target, replays=2), _plan_reference(case, target), "edge plan")
 
 
 def test_registration_loop():
