@@ -712,10 +712,13 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             // branch-free: outside [1, S) rho = 0, so the pixel is 0 and v1
             // unchanged (make_map)
             const int k = t0 + base + i;
+            // the chunk states and the gains below are read once, by the
+            // adjoint after the blur: non-temporal stores keep them from
+            // displacing the volume and the images in the caches
             if ((i % kStateStride) == 0 && qs) {
-                qs[i / kStateStride] = v0;
-                qs[kStatesPerBlock + i / kStateStride] = v1;
-                qs[2 * kStatesPerBlock + i / kStateStride] = D;
+                __builtin_nontemporal_store(v0, qs + i / kStateStride);
+                __builtin_nontemporal_store(v1, qs + kStatesPerBlock + i / kStateStride);
+                __builtin_nontemporal_store(D, qs + 2 * kStatesPerBlock + i / kStateStride);
             }
             const double r = s_rho[pad8(base + i)];
             const Map m = make_map(r, a2, sgn);
@@ -782,8 +785,13 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
                 const int i = 4 * q;
                 *reinterpret_cast<float4 *>(out + o + i) =
                     make_float4(pix[i] * gn[i], pix[i + 1] * gn[i + 1], pix[i + 2] * gn[i + 2], pix[i + 3] * gn[i + 3]);
-                if (has_gain && gain_out)
-                    *reinterpret_cast<float4 *>(gain_out + o + i) = make_float4(gn[i], gn[i + 1], gn[i + 2], gn[i + 3]);
+                if (has_gain && gain_out) {
+                    float *gq = gain_out + o + i;
+                    __builtin_nontemporal_store(gn[i], gq);
+                    __builtin_nontemporal_store(gn[i + 1], gq + 1);
+                    __builtin_nontemporal_store(gn[i + 2], gq + 2);
+                    __builtin_nontemporal_store(gn[i + 3], gq + 3);
+                }
             }
         } else {
 #pragma unroll
