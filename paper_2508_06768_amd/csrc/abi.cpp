@@ -208,6 +208,7 @@ struct WsLayout {
     size_t eb = 0, eb_bytes = 0;       // blur-transposed dL/dI (adjoint with blur)
     size_t res = 0, res_bytes = 0;     // MSE residual (plan with blur)
     size_t acc = 0, acc_bytes = 0;     // pose accumulators
+    size_t rp = 0, rp_bytes = 0;       // per-ray pose partials of one table (adjoint)
     size_t zb = 0, zb_bytes = 0;       // dL/dZ per sample (adjoint)
     size_t part = 0, part_bytes = 0;   // loss partials (plan step)
     size_t car = 0, car_bytes = 0;     // tile carries, 4 doubles per record (plan step)
@@ -245,6 +246,12 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         L.acc = off;
         L.acc_bytes = (size_t)std::max(n_poses, 1) * dus::kPoseAcc * sizeof(double);
         off = align_up(off + L.acc_bytes);
+        // the tables run one after the other, so one table's worth is enough
+        size_t rays = 1;
+        for (const auto &t : build_tables(fans, n_poses)) rays = std::max(rays, (size_t)t.total_rays);
+        L.rp = off;
+        L.rp_bytes = rays * dus::kRayPart * sizeof(double);
+        off = align_up(off + L.rp_bytes);
     }
     if (mode == 2) {
         // one partial per blur block or per ray of every table
@@ -436,7 +443,8 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
         for (const auto &t : tabs)
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, src, nullptr,
                                          reinterpret_cast<float *>((char *)ws + L.zb), grad_Z,
-                                         grad_pose ? acc : nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, st),
+                                         grad_pose ? acc : nullptr, reinterpret_cast<double *>((char *)ws + L.rp),
+                                         nullptr, nullptr, nullptr, nullptr, nullptr, st),
                     "adjoint kernel launch");
     }
     if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel launch");
@@ -713,6 +721,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     const dus::PhysArgs pa = phys_args(&p->phys);
     const int n_poses = (int)p->fans.size();
     double *acc = reinterpret_cast<double *>((char *)ws + p->ws.acc);
+    double *rpart = reinterpret_cast<double *>((char *)ws + p->ws.rp);
     float *zbar = reinterpret_cast<float *>((char *)ws + p->ws.zb);
     float *gZ = (p->flags & DUS_PLAN_POSE_ONLY) ? nullptr : grad_Z;
     double *part = reinterpret_cast<double *>((char *)ws + p->ws.part);
@@ -760,7 +769,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     if (adj)
         for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, blur ? nullptr : target, zbar,
-                                        grad_pose ? acc : nullptr, (!blur && loss) ? part + n_part : nullptr,
+                                        grad_pose ? acc : nullptr, rpart, (!blur && loss) ? part + n_part : nullptr,
                                         fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? cst : nullptr,
                                         fwd ? gain : nullptr, st),
                     "adjoint kernel");

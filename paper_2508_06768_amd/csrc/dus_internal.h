@@ -73,6 +73,9 @@ struct PhysArgs {
 
 // Per-pose accumulator of the adjoint: dL/dt (3) and dL/dR (9), FP64.
 constexpr int kPoseAcc = 12;
+// Per-ray partial of the adjoint: dL/dt (3) and the two non-zero columns of
+// dL/dR (the ray direction has no y component in the probe frame), FP64.
+constexpr int kRayPart = 9;
 
 // Launch wrappers (kernels.hip).  All enqueue on `st` and return the HIP
 // error of the launch.
@@ -84,18 +87,20 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
                           float *min_pivot, int pivot_base, double *carry, int32_t *carry_exp,
                           double *cstate, float *gain, hipStream_t st);
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
-// the fused form (target given) loss receives one partial per ray
+// the fused form (target given) loss receives one partial per ray.  With
+// pose_acc, pose_part (kRayPart doubles per ray of the table) holds the
+// per-ray pose partials, which are then added into pose_acc.
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
-                           double *pose_acc, double *loss, const double *carry,
+                           double *pose_acc, double *pose_part, double *loss, const double *carry,
                            const int32_t *carry_exp, const double *cstate, const float *gain,
                            hipStream_t st);
 // the two halves of launch_backward: the adjoint scan (dL/dZ per sample into
 // zbar, pose sums, fused loss partials) and the scatter of zbar into gZ
 hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, const float *gsrc,
-                          const float *target, float *zbar, double *pose_acc, double *loss,
+                          const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
                           const float *gain, hipStream_t st);
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,

@@ -849,7 +849,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                                                  const float *__restrict__ gsrc,
                                                  const float *__restrict__ target,
                                                  float *__restrict__ zbar,
-                                                 double *__restrict__ pose_acc,
+                                                 double *__restrict__ pose_part,
                                                  double *__restrict__ loss_acc,
                                                  const double *__restrict__ carry,
                                                  const int32_t *__restrict__ carry_exp,
@@ -990,7 +990,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                 Ds = (k == 0) ? 1.0 : q[2 * kStatesPerBlock];
             }
         }
-        if (pose_acc)
+        if (pose_part)
             gather_tile<C, true, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, nullptr, s_dq);
         else
             gather_tile<C, true, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, nullptr, nullptr, s_dq);
@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             const double qr = (k + 1 < S) ? ((i + 1 < T) ? s_rho[pad8(i + 1)] : rbar_next) : 0.0;
             const double zb = fma(-qr, zr, ql * zl);
             if (k < S) zbar[obase + k] = (float)zb;
-            if (pose_acc) {
+            if (pose_part) {
                 // dL/dp = zb dZ/dp; dL/dR accumulates (s_k dir) outer dL/dp
                 const double sk = fma((double)k, ray.ds, ray.r0);
 #pragma unroll
@@ -1246,7 +1246,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         z_next = lane_read(s_z[pad8(lane)], 0);
         __syncthreads();
     }
-    if (pose_acc) {
+    if (pose_part) {
         double r[6];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1254,13 +1254,15 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             r[3 + a] = wave_sum(gssum[a]);
         }
         if (lane == 0) {
-            double *pa = pose_acc + (size_t)kPoseAcc * fr.pose;
-            // dL/dt = sum g;  dL/dR = sum g (s dir)^T, dir = (sx, 0, cz)
+            // this ray's share of dL/dt = sum g and dL/dR = sum g (s dir)^T,
+            // dir = (sx, 0, cz); k_pose_reduce sums the rays of each pose
+            // (in a fixed order: no contended atomics on the pose's entries)
+            double *pr = pose_part + (size_t)kRayPart * g;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                atomicAdd(pa + a, r[a]);
-                atomicAdd(pa + 3 + 3 * a + 0, r[3 + a] * ray.dirx);
-                atomicAdd(pa + 3 + 3 * a + 2, r[3 + a] * ray.dirz);
+                pr[a] = r[a];
+                pr[3 + 2 * a] = r[3 + a] * ray.dirx;
+                pr[4 + 2 * a] = r[3 + a] * ray.dirz;
             }
         }
     }
@@ -1698,6 +1700,34 @@ __global__ void k_pose_finalize(const double *__restrict__ acc, const float *__r
     if (pi < n) pose_finalize_one(acc, poses, pi, grad);
 }
 
+// one wavefront per fan of a table: the per-ray partials of the adjoint
+// summed into the pose's accumulator (lane-strided, then across lanes)
+__global__ __launch_bounds__(64) void k_pose_reduce(FanTable tab, const double *__restrict__ part,
+                                                    double *__restrict__ acc)
+{
+    const FanRec fr = tab.f[blockIdx.x];
+    const int lane = threadIdx.x;
+    double s[kRayPart];
+#pragma unroll
+    for (int c = 0; c < kRayPart; ++c) s[c] = 0.0;
+    for (int j = lane; j < fr.n_rays; j += 64) {
+        const double *pr = part + (size_t)kRayPart * (fr.ray_begin + j);
+#pragma unroll
+        for (int c = 0; c < kRayPart; ++c) s[c] += pr[c];
+    }
+#pragma unroll
+    for (int c = 0; c < kRayPart; ++c) s[c] = wave_sum(s[c]);
+    if (lane == 0) {
+        double *pa = acc + (size_t)kPoseAcc * fr.pose;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            pa[a] += s[a];
+            pa[3 + 3 * a + 0] += s[3 + 2 * a];
+            pa[3 + 3 * a + 2] += s[4 + 2 * a];
+        }
+    }
+}
+
 // --------------------------------------------------------------------------
 // footprint: mark every stencil corner of every sample
 // --------------------------------------------------------------------------
@@ -2112,8 +2142,8 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 #define DUS_BWD_LAUNCH(CH, SPK, FUSED)                                                          \
     hipLaunchKernelGGL((k_backward<CH, SPK, FUSED>), dim3(grid), dim3(64), 0, st, v, p, t,      \
-                       poses, gsrc, target, zbar, pose_acc, loss, carry, carry_exp, cstate, gain,        \
-                       xcd_group)
+                       poses, gsrc, target, zbar, pose_acc ? pose_part : nullptr, loss, carry,           \
+                       carry_exp, cstate, gain, xcd_group)
 
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
@@ -2128,12 +2158,13 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, const float *gsrc,
-                          const float *target, float *zbar, double *pose_acc, double *loss,
+                          const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
                           const float *gain, hipStream_t st)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
+    if (pose_acc && !pose_part) return hipErrorInvalidValue;
     const bool fused = (target != nullptr);
     const bool spk = p.speckle && !gain;      // recorded gains replace the speckle variates
     if (!carry) cstate = nullptr;             // chunk states are read in the frames of the carry records
@@ -2143,6 +2174,9 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
     default:
         return hipErrorInvalidValue;
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !pose_acc) return e;
+    hipLaunchKernelGGL(k_pose_reduce, dim3(t.n), dim3(64), 0, st, t, pose_part, pose_acc);
     return hipGetLastError();
 }
 
@@ -2186,12 +2220,12 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
-                           double *pose_acc, double *loss, const double *carry,
+                           double *pose_acc, double *pose_part, double *loss, const double *carry,
                            const int32_t *carry_exp, const double *cstate, const float *gain,
                            hipStream_t st)
 {
-    hipError_t e = launch_adjoint(chunk, xcd_group, v, p, t, poses, gsrc, target, zbar, pose_acc, loss, carry,
-                                  carry_exp, cstate, gain, st);
+    hipError_t e = launch_adjoint(chunk, xcd_group, v, p, t, poses, gsrc, target, zbar, pose_acc, pose_part, loss,
+                                  carry, carry_exp, cstate, gain, st);
     if (e != hipSuccess) return e;
     return launch_scatter(scatter_rays, xcd_group, v, t, poses, zbar, gZ, st);
 }
