@@ -152,7 +152,9 @@ def test_workspace_sizes():
     p = _phys()
     assert L.dus_workspace_bytes(ctypes.byref(v), f, 2, ctypes.byref(p), 0) == 0
     wb = L.dus_workspace_bytes(ctypes.byref(v), f, 2, ctypes.byref(p), 1)
-    assert wb >= 2 * 12 * 8 and wb % 256 == 0
+    # the adjoint's dL/dZ per sample (550 floats), the pose accumulators
+    # (12 doubles per pose) and the per-ray pose partials (9 doubles per ray)
+    assert wb >= 550 * 4 + 2 * 12 * 8 + 7 * 9 * 8 and wb % 256 == 0
     pb = _phys(blur_on=1)
     wfb = L.dus_workspace_bytes(ctypes.byref(v), f, 2, ctypes.byref(pb), 0)
     assert wfb >= 550 * 4 and wfb % 256 == 0
