@@ -246,9 +246,9 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         L.acc = off;
         L.acc_bytes = (size_t)std::max(n_poses, 1) * dus::kPoseAcc * sizeof(double);
         off = align_up(off + L.acc_bytes);
-        // the tables run one after the other, so one table's worth is enough
+        // every table's rays: the partials are summed after all adjoints ran
         size_t rays = 1;
-        for (const auto &t : build_tables(fans, n_poses)) rays = std::max(rays, (size_t)t.total_rays);
+        for (const auto &t : build_tables(fans, n_poses)) rays += (size_t)t.total_rays;
         L.rp = off;
         L.rp_bytes = rays * dus::kRayPart * sizeof(double);
         off = align_up(off + L.rp_bytes);
@@ -440,12 +440,23 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
             for (const auto &t : tabs) DUS_HIP(dus::launch_blur(true, pa, t, grad_bmode, eb, st), "blur^T kernel launch");
             src = eb;
         }
-        for (const auto &t : tabs)
+        double *rpart = reinterpret_cast<double *>((char *)ws + L.rp);
+        int64_t r0 = 0;
+        for (const auto &t : tabs) {
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, src, nullptr,
                                          reinterpret_cast<float *>((char *)ws + L.zb), grad_Z,
-                                         grad_pose ? acc : nullptr, reinterpret_cast<double *>((char *)ws + L.rp),
-                                         nullptr, nullptr, nullptr, nullptr, nullptr, st),
+                                         grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0, nullptr, nullptr,
+                                         nullptr, nullptr, nullptr, st),
                     "adjoint kernel launch");
+            r0 += t.total_rays;
+        }
+        if (grad_pose) {
+            r0 = 0;
+            for (const auto &t : tabs) {
+                DUS_HIP(dus::launch_pose_reduce(t, rpart + dus::kRayPart * r0, acc, st), "pose reduction kernel");
+                r0 += t.total_rays;
+            }
+        }
     }
     if (grad_pose) DUS_HIP(dus::launch_pose_finalize(acc, poses, n_poses, grad_pose, st), "pose kernel launch");
     return DUS_OK;
@@ -766,20 +777,30 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     // with blur the adjoint starts from B^T of the residual; without it, the
     // adjoint forms the residual and the loss partials itself
     const bool adj = blur ? (gZ || grad_pose) : true;
+    int64_t r0 = 0;        // rays of the tables before this one (pose partials)
     if (adj)
         for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, blur ? nullptr : target, zbar,
-                                        grad_pose ? acc : nullptr, rpart, (!blur && loss) ? part + n_part : nullptr,
+                                        grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0,
+                                        (!blur && loss) ? part + n_part : nullptr,
                                         fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? cst : nullptr,
                                         fwd ? gain : nullptr, st),
                     "adjoint kernel");
             if (!blur) n_part += t.total_rays;
+            r0 += t.total_rays;
         }
     DUS_HIP(mark(DUS_PHASE_SCATTER), "event");
     if (adj && gZ)
         for (const auto &t : p->tabs)
             DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, poses, zbar, gZ, st), "scatter kernel");
     DUS_HIP(mark(DUS_PHASE_FINISH), "event");
+    if (adj && grad_pose) {
+        r0 = 0;
+        for (const auto &t : p->tabs) {
+            DUS_HIP(dus::launch_pose_reduce(t, rpart + dus::kRayPart * r0, acc, st), "pose reduction kernel");
+            r0 += t.total_rays;
+        }
+    }
     DUS_HIP(dus::launch_finish(part, n_part, loss, acc, poses, n_poses, grad_pose, st), "loss and pose kernel");
     DUS_HIP(mark(DUS_NUM_PHASES), "event");
     return DUS_OK;

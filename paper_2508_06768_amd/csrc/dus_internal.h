@@ -88,8 +88,8 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
                           double *cstate, float *gain, hipStream_t st);
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
 // the fused form (target given) loss receives one partial per ray.  With
-// pose_acc, pose_part (kRayPart doubles per ray of the table) holds the
-// per-ray pose partials, which are then added into pose_acc.
+// pose_acc (a flag here), pose_part receives kRayPart doubles per ray of the
+// table; launch_pose_reduce then adds them into the pose accumulators.
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
                            const PhysArgs &p, const FanTable &t, const float *poses,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
@@ -103,6 +103,9 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
                           const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
                           const float *gain, hipStream_t st);
+// pose_acc[pose] += the sum of the table's per-ray partials, one wavefront
+// per fan (fixed order)
+hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double *pose_acc, hipStream_t st);
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
                           const float *poses, const float *zbar, float *gZ, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,

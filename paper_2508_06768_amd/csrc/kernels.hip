@@ -2174,8 +2174,12 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
     default:
         return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !pose_acc) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double *pose_acc, hipStream_t st)
+{
+    if (t.n <= 0 || t.total_rays <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pose_reduce, dim3(t.n), dim3(64), 0, st, t, pose_part, pose_acc);
     return hipGetLastError();
 }

@@ -201,6 +201,33 @@ def test_fused_plan_matches_oracle():
         _check_plan(case, _run_plan(case, target), _plan_reference(case, target), f"plan fx={effects}")
 
 
+def test_plan_with_two_fan_tables():
+    """70 fans: more than one launch table (64 fans each), so the tables'
+    carry records, loss partials and per-ray pose partials sit at offsets.
+    The fused step (with blur) and render + adjoint against the oracle."""
+    from paper_2508_06768_amd.render import render, render_backward
+    Z = synth.brain_volume(17, 40, 1.0, semi_range=(3.0, 9.0))
+    rng = np.random.default_rng(17)
+    P = 70
+    poses = np.concatenate([rng.uniform(14.0, 25.0, (P, 2)), rng.uniform(0.0, 2.0, (P, 1)),
+                            rng.uniform(-0.2, 0.2, (P, 3))], axis=1).astype(np.float32)
+    fans = [synth.FanSpec(int(rng.integers(1, 9)), int(rng.integers(20, 300)), 0.8, 0.13, 0.0, p) for p in range(P)]
+    for effects in (False, True):
+        case = synth.Case("tables70", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans,
+                          synth.PhysicsSpec(speckle_on=effects, blur_on=effects, seed=17))
+        target = H.oracle_render(case, poses=case.poses + np.float32([[0.4, -0.3, 0.2, 0.01, 0.0, -0.02]]))
+        _check_plan(case, _run_plan(case, target, replays=2), _plan_reference(case, target), f"70 fans fx={effects}")
+        geom, Zt, Pt = _gpu(case)
+        _check_images(render(Zt, Pt, geom).cpu().numpy(), H.oracle_render(case), "70 fans render", case.fans)
+        w = rng.standard_normal(geom.total).astype(np.float32)
+        gZ, gp = render_backward(Zt, Pt, geom, torch.from_numpy(w).to(DEV))
+        rV, rp = H.oracle_backward(case, w.astype(np.float64))
+        assert H.rel_l2(gZ.cpu().numpy(), rV) <= RTOL_GRAD
+        gpn = gp.cpu().numpy()
+        for q in range(P):
+            assert np.all(np.abs(gpn[q] - rp[q]) <= RTOL_GRAD * np.linalg.norm(rp[q]) + 1e-30)
+
+
 def rough_column_case(refl, effects, seed=13) -> synth.Case:
     """A 1100 x 8 x 8 column of independent uniform voxels crossed one voxel
     per sample (U(1.4, 1.8) in the |R| convention, U(1, 3) signed): every
