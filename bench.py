@@ -101,9 +101,35 @@ def cpu_baseline(case, budget_s: float):
             break
     dt = time.perf_counter() - t0
     threads = O.num_threads()
-    return {"value": samples / dt, "unit": "ray-samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} pose steps ({done / len(fans):.1f} passes over the {len(fans)} poses, 256x1024 "
-                      f"each), FP64 forward + MSE + adjoint (dL/dZ and dL/dpose), {dt:.1f} s"}
+    out = {"value": samples / dt, "unit": "ray-samples/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done} pose steps ({done / len(fans):.1f} passes over the {len(fans)} poses, 256x1024 "
+                     f"each), FP64 forward + MSE + adjoint (dL/dZ and dL/dpose), {dt:.1f} s"}
+    # the same oracle: forward only on all threads, forward + adjoint on one
+    # thread (one pose each), and the literal O(S^2) progressive solve of
+    # Sec. 2.4 on the 64^3 phantom's 64 x 256 fan, once
+    t1 = time.perf_counter()
+    nf = 0
+    while nf < 4 or time.perf_counter() - t1 < 1.0:
+        O.render(vol, case.poses[nf % len(fans)].astype(np.float64), fans[nf % len(fans)], ph)
+        nf += 1
+    out["forward_value"] = nf * fans[0].n_rays * fans[0].n_samples / (time.perf_counter() - t1)
+    O.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        img = O.render(vol, case.poses[0].astype(np.float64), fans[0], ph)
+        _, g = O.mse_loss_grad(img, np.zeros_like(img))
+        O.backward(vol, case.poses[0].astype(np.float64), fans[0], ph, g)
+        out["single_thread_value"] = fans[0].n_rays * fans[0].n_samples / (time.perf_counter() - t1)
+    finally:
+        O.set_num_threads(threads)
+    from paper_2508_06768_amd import synth
+    c1 = synth.case_small_forward()
+    v1, f1, p1 = H.oracle_volume(c1), H.oracle_fan(c1.fans[0]), H.oracle_physics(c1.phys)
+    for solver in ("transfer", "banded"):
+        t1 = time.perf_counter()
+        O.render(v1, c1.poses[0].astype(np.float64), f1, p1, solver=solver)
+        out[f"phantom_64x256_forward_{solver}_s"] = time.perf_counter() - t1
+    return out
 
 
 def main():

@@ -744,3 +744,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the thread count of the parallel loops (no effect without OpenMP). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -81,6 +81,7 @@ def lib():
         _lib.orc_backward.restype = ctypes.c_int
         _lib.orc_blur_radius.restype = ctypes.c_int
         _lib.orc_num_threads.restype = ctypes.c_int
+        _lib.orc_set_num_threads.restype = None
         del d
     return _lib
 
@@ -88,6 +89,11 @@ def lib():
 def num_threads() -> int:
     """Threads of the oracle's OpenMP loops."""
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops from now on (timing only)."""
+    lib().orc_set_num_threads(ctypes.c_int(int(n)))
 
 
 def _dp(a: np.ndarray):
