@@ -221,8 +221,10 @@ def test_graph_replays_agree():
     for r in res:
         np.testing.assert_array_equal(r[0], ref[0])
         assert r[1] == pytest.approx(ref[1], rel=1e-12)
+        # dL/dZ goes through the scatter's global atomics (order-dependent
+        # rounding); the pose gradient is summed in a fixed order
         assert H.rel_l2(r[2], ref[2]) <= 1e-6
-        assert H.rel_l2(r[3], ref[3]) <= 1e-6
+        np.testing.assert_array_equal(r[3], ref[3])
 
 
 def test_binding_rejects_short_buffers():
