@@ -2016,19 +2016,27 @@ __global__ __launch_bounds__(256) void k_map(const float *__restrict__ in, long 
 // dL/dz_{j+1} += t dL/dZ, or all of dL/dZ to the end knot beyond an end.
 // The knot sums go through an FP64 LDS copy per block, then one global FP64
 // atomic per knot and block.
+// The table gradient is a histogram over the knots.  Its LDS accumulators
+// are replicated 8 times (lane % 8 picks the copy, rows padded to 65 so the
+// copies of one knot sit in different banks): lanes of one wavefront that
+// meet on a knot mostly add into different copies instead of serialising on
+// one address.
+constexpr int kMapCopies = 8, kMapRow = kMaxKnots + 1;
+
 __global__ __launch_bounds__(256) void k_map_backward(const float *__restrict__ in, long long n, LutArgs lut,
                                                       const float *__restrict__ gZ, float *__restrict__ grad_in,
                                                       double *__restrict__ grad_z)
 {
     __shared__ float s_x[kMaxKnots], s_z[kMaxKnots];
-    __shared__ double s_g[kMaxKnots];
+    __shared__ double s_g[kMapCopies * kMapRow];
     const int m = lut.n;
     for (int i = threadIdx.x; i < m; i += 256) {
         s_x[i] = lut.x[i];
         s_z[i] = lut.z[i];
-        s_g[i] = 0.0;
     }
+    for (int i = threadIdx.x; i < kMapCopies * kMapRow; i += 256) s_g[i] = 0.0;
     __syncthreads();
+    double *g_own = s_g + (threadIdx.x % kMapCopies) * kMapRow;
     const float x0 = s_x[0], xn = s_x[m - 1];
     const int top = lut_top(m);
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
@@ -2036,25 +2044,29 @@ __global__ __launch_bounds__(256) void k_map_backward(const float *__restrict__ 
         const float g = gZ[i];
         float gi = 0.0f;
         if (v <= x0) {
-            if (grad_z) atomicAdd(&s_g[0], (double)g);
+            if (grad_z) atomicAdd(&g_own[0], (double)g);
         } else if (v >= xn) {
-            if (grad_z) atomicAdd(&s_g[m - 1], (double)g);
+            if (grad_z) atomicAdd(&g_own[m - 1], (double)g);
         } else {
             const int j = lut_segment(s_x, top, m, v);
             const float dx = s_x[j + 1] - s_x[j];
             gi = g * __fdiv_rn(s_z[j + 1] - s_z[j], dx);
             if (grad_z) {
                 const double t = (double)__fdiv_rn(v - s_x[j], dx);
-                atomicAdd(&s_g[j], (1.0 - t) * (double)g);
-                atomicAdd(&s_g[j + 1], t * (double)g);
+                atomicAdd(&g_own[j], (1.0 - t) * (double)g);
+                atomicAdd(&g_own[j + 1], t * (double)g);
             }
         }
         if (grad_in) grad_in[i] = gi;
     }
     if (grad_z) {
         __syncthreads();
-        for (int k = threadIdx.x; k < m; k += 256)
-            if (s_g[k] != 0.0) atomicAdd(grad_z + k, s_g[k]);
+        for (int k = threadIdx.x; k < m; k += 256) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < kMapCopies; ++c) t += s_g[c * kMapRow + k];
+            if (t != 0.0) atomicAdd(grad_z + k, t);
+        }
     }
 }
 
