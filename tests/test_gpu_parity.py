@@ -73,6 +73,12 @@ def test_philox_bitexact():
     out = philox(torch.from_numpy(ctr.view(np.int32)).to(DEV), seed).cpu().numpy().view(np.uint32)
     ref = O.philox(ctr, [seed & 0xFFFFFFFF, seed >> 32])
     np.testing.assert_array_equal(out, ref)
+    # and the generator's published known-answer vectors
+    from tests.test_oracle_pins import philox_kat
+    kc, kk, kr = philox_kat()
+    for c, k, r in zip(kc, kk, kr):
+        got = philox(torch.from_numpy(c[None].copy().view(np.int32)).to(DEV), int(k[0]) | (int(k[1]) << 32))
+        np.testing.assert_array_equal(got.cpu().numpy().view(np.uint32).reshape(-1), r)
 
 
 @pytest.mark.parametrize("atten", [0, 1])
