@@ -723,7 +723,9 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
             const double r = s_rho[pad8(base + i)];
             const Map m = make_map(r, a2, sgn);
             const double v1n = fma(v0, r, v1);
-            pix[i] = (float)(r * D * rcp64(v1 * v1n));
+            // the pixel leaves in FP32: the hardware FP64 reciprocal, without
+            // the Newton step, is accurate well beyond that
+            pix[i] = (float)(r * D * __builtin_amdgcn_rcp(v1 * v1n));
             if (want_piv) piv = (k >= 1 && k < S) ? fmin(piv, fabs(v1n * rcp64(v1))) : piv;
             const double v0n = fma(v0, m.m00, v1 * m.m10);
             v0 = v0n;
