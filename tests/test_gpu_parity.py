@@ -169,19 +169,19 @@ def _plan_reference(case, target):
     return img, ref_loss, rV, rp
 
 
-def _run_plan(case, target, schedule=None, replays=3):
+def _run_plan(case, target, schedule=None, replays=3, image=True):
     from paper_2508_06768_amd.render import FusedStep
     geom, Z, poses = _gpu(case)
     T = torch.from_numpy(target.astype(np.float32)).to(DEV)
     step = FusedStep(geom, zero_grad_z=True, schedule=schedule)
-    bm = torch.empty(geom.total, device=DEV)
+    bm = torch.empty(geom.total, device=DEV) if image else None
     loss = torch.zeros(1, dtype=torch.float64, device=DEV)
     gZ = torch.full_like(Z, 123.0)
     gp = torch.empty((geom.n_poses, 6), device=DEV)
     for _ in range(replays):                    # replays of the same graph
         step.step(Z, poses, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
     torch.cuda.synchronize()
-    out = (bm.cpu().numpy(), loss.item(), gZ.cpu().numpy(), gp.cpu().numpy())
+    out = (bm.cpu().numpy() if image else None, loss.item(), gZ.cpu().numpy(), gp.cpu().numpy())
     step.close()
     return out
 
@@ -189,7 +189,8 @@ def _run_plan(case, target, schedule=None, replays=3):
 def _check_plan(case, got, ref, tag):
     bm, loss, gZ, gp = got
     img, ref_loss, rV, rp = ref
-    _check_images(bm, img, f"{tag} image", case.fans)
+    if bm is not None:
+        _check_images(bm, img, f"{tag} image", case.fans)
     assert loss == pytest.approx(ref_loss, rel=1e-5)
     e = H.rel_l2(gZ, rV)
     print(tag, "dZ rel l2", e, flush=True)
@@ -205,6 +206,15 @@ def test_fused_plan_matches_oracle():
         tgt_poses = case.poses + np.float32([[0.6, -0.3, 0.2, 0.02, -0.03, 0.05]])
         target = H.oracle_render(case, poses=tgt_poses)
         _check_plan(case, _run_plan(case, target), _plan_reference(case, target), f"plan fx={effects}")
+
+
+def test_fused_plan_without_image():
+    """No blur and no image requested: the forward kernel does not run, and
+    the fused adjoint forms the residual and the loss itself, starting from
+    its own forward sweep (no carries or chunk states)."""
+    case = ragged_case(1, 0, False, seed=23)
+    target = H.oracle_render(case, poses=case.poses + np.float32([[0.5, 0.2, -0.3, 0.0, 0.03, 0.0]]))
+    _check_plan(case, _run_plan(case, target, image=False), _plan_reference(case, target), "plan, no image")
 
 
 def test_plan_with_two_fan_tables():
