@@ -393,6 +393,9 @@ static double rayleigh(uint32_t x)
     return sqrt(-2.0 * log(u)) * sqrt(2.0 / M_PI);
 }
 
+/* the same map, exported for its pins */
+double orc_rayleigh(uint32_t x) { return rayleigh(x); }
+
 static uint32_t philox_word(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed, int w)
 {
     uint32_t ctr[4] = {c0, c1, c2, c3}, key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, out[4];

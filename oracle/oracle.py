@@ -81,6 +81,8 @@ def lib():
         _lib.orc_backward.restype = ctypes.c_int
         _lib.orc_blur_radius.restype = ctypes.c_int
         _lib.orc_num_threads.restype = ctypes.c_int
+        _lib.orc_rayleigh.restype = ctypes.c_double
+        _lib.orc_rayleigh.argtypes = [ctypes.c_uint32]
         _lib.orc_set_num_threads.restype = None
         del d
     return _lib
@@ -202,12 +204,23 @@ def render(vol: Volume, pose, fan: Fan, phys: Physics, solver: str = "transfer",
 
 
 def backward(vol: Volume, pose, fan: Fan, phys: Physics, grad_img: np.ndarray,
-             want_volume: bool = True):
-    """dL/dZ (volume, FP64) and dL/dpose (t_xyz mm, w_xyz rad) for dL/dimg."""
+             want_volume: bool = True, grad_volume: np.ndarray | None = None):
+    """dL/dZ (volume, FP64) and dL/dpose (t_xyz mm, w_xyz rad) for dL/dimg.
+
+    grad_volume: optional C-contiguous FP64 array of the volume's shape that
+    receives dL/dZ added in place (the C routine accumulates); it is then
+    the returned volume gradient.  Without it a zeroed one is allocated."""
     L = lib()
     p = _pose(pose)
     g = np.ascontiguousarray(grad_img, dtype=np.float64).reshape(fan.n_rays, fan.n_samples)
-    gV = np.zeros_like(vol.Z) if want_volume else None
+    gV = None
+    if grad_volume is not None:
+        if (grad_volume.dtype != np.float64 or grad_volume.shape != vol.Z.shape
+                or not grad_volume.flags["C_CONTIGUOUS"]):
+            raise ValueError("grad_volume must be a C-contiguous float64 array of the volume's shape")
+        gV = grad_volume
+    elif want_volume:
+        gV = np.zeros_like(vol.Z)
     gp = np.zeros(6, dtype=np.float64)
     cv, cf, cp = vol.c(), fan.c(), phys.c()
     rc = L.orc_backward(ctypes.byref(cv), _dp(p), ctypes.byref(cf), ctypes.byref(cp), _dp(g),
@@ -402,6 +415,12 @@ def philox(counters: np.ndarray, key) -> np.ndarray:
     lib().orc_philox_batch(c.ctypes.data_as(u32p), ctypes.c_int64(c.shape[0]), k.ctypes.data_as(u32p),
                            out.ctypes.data_as(u32p))
     return out
+
+
+def rayleigh(word: int) -> float:
+    """Unit-mean Rayleigh variate of one 32-bit generator word (the map the
+    speckle multipliers use)."""
+    return float(lib().orc_rayleigh(ctypes.c_uint32(int(word) & 0xFFFFFFFF)))
 
 
 def speckle_ray(fan: Fan, phys: Physics, j: int) -> np.ndarray:

@@ -369,6 +369,94 @@ def test_philox_known_answers():
         np.testing.assert_array_equal(O.philox(c[None], list(k)).reshape(-1), r)
 
 
+def test_philox_known_answers_match_rocrand(tmp_path):
+    """The known-answer file's outputs are also what rocRAND's open-source
+    Philox4x32-10 computes for its counters and keys (a second, independent
+    source for the stored values)."""
+    exe = _rocrand_ref(tmp_path)
+    ctr, keys, out = philox_kat()
+    lines = "\n".join(" ".join(str(int(v)) for v in list(c) + list(k)) for c, k in zip(ctr, keys))
+    got = subprocess.run([exe], input=lines, capture_output=True, text=True, check=True).stdout
+    ref = np.array([[int(v) for v in ln.split()] for ln in got.strip().splitlines()], dtype=np.uint64)
+    np.testing.assert_array_equal(ref, out.astype(np.uint64))
+
+
+def test_rayleigh_map_closed_forms():
+    """The speckle's unit-mean Rayleigh variate of a 32-bit word, pinned
+    where its uniform u = ((x >> 8) + 1) 2^-24 has a closed form, and by the
+    survival function of the unit-mean Rayleigh law, P(xi > x) =
+    exp(-pi x^2 / 4) (scale sigma^2 = 2/pi): the map must invert it,
+    exp(-pi xi(u)^2 / 4) = u, and fall as the word's top 24 bits rise."""
+    import math
+    # top 24 bits all set: u = 1, xi = 0 exactly
+    for x in (0xFFFFFF00, 0xFFFFFF7A, 0xFFFFFFFF):
+        assert O.rayleigh(x) == 0.0
+    # top 24 bits clear: u = 2^-24, -2 ln u = 48 ln 2
+    for x in (0, 1, 255):
+        assert O.rayleigh(x) == pytest.approx(math.sqrt(48.0 * math.log(2.0)) / math.sqrt(math.pi / 2.0),
+                                              rel=1e-15)
+    # (x >> 8) + 1 = 2^23: u = 1/2
+    assert O.rayleigh((2 ** 23 - 1) << 8) == pytest.approx(
+        math.sqrt(2.0 * math.log(2.0)) / math.sqrt(math.pi / 2.0), rel=1e-15)
+    rng = np.random.default_rng(90)
+    words = np.sort(rng.integers(0, 2 ** 32, size=2000, dtype=np.uint64))
+    xi = np.array([O.rayleigh(int(w)) for w in words])
+    u = ((words >> 8).astype(np.float64) + 1.0) / 2.0 ** 24
+    np.testing.assert_allclose(np.exp(-np.pi * xi * xi / 4.0), u, rtol=1e-12)
+    assert np.all(np.diff(xi) <= 0.0)
+
+
+def _speckle_words(fan, ph, j, term, n):
+    """Rayleigh variates of the first n indices of one speckle stream:
+    index i sits in word i & 3 of the Philox block at counter
+    (i >> 2, ray j, fan id, term), key = the seed's two halves."""
+    key = [ph.seed & 0xFFFFFFFF, ph.seed >> 32]
+    ctr = np.array([[i >> 2, j, fan.speckle_id, term] for i in range(n)], dtype=np.uint32)
+    w = O.philox(ctr, key)
+    return np.array([O.rayleigh(int(w[i, i & 3])) for i in range(n)])
+
+
+@pytest.mark.parametrize("gamma", [0.0, 1.0, 2.5])
+def test_speckle_radial_term_closed_form(gamma):
+    """The radial term alone (Ar = 1, Ag0 = Ag1 = 0).  At a cell boundary
+    k = c cell the multiplier is 1 + zeta^gamma (xi_r(c) - 1) with
+    zeta = k / (S - 1) and xi_r(c) the variate of radial stream index c;
+    inside a cell, m - 1 = zeta^gamma (x - 1) with x linear in the cell
+    fraction between the two boundary values.  A wrong exponent, cell index
+    or counter word fails one of the two.  (m - 1 is compared in absolute
+    terms: m is about 1, so its last bit is about 2^-52.)"""
+    S, cell = 203, 8
+    fan = O.Fan(4, S, 1.0, 0.2, 0.0, 5)
+    ph = O.Physics(speckle_on=True, Ar=1.0, gamma=gamma, Ag0=0.0, Ag1=0.0, spk_cell=cell, seed=0x1234_5678_9ABC)
+    k = np.arange(S)
+    zeta = k / (S - 1)
+    pw = np.where(zeta > 0, zeta ** gamma, 1.0 if gamma == 0.0 else 0.0)
+    for j in (0, 3):
+        m = O.speckle_ray(fan, ph, j)
+        xr = _speckle_words(fan, ph, j, 1, (S - 1) // cell + 2)
+        edge = k[(k % cell) == 0]
+        np.testing.assert_allclose(m[edge] - 1.0, pw[edge] * (xr[edge // cell] - 1.0), rtol=1e-13, atol=1e-15)
+        inner = k[(k % cell) != 0]
+        c, f = inner // cell, (inner % cell) / cell
+        np.testing.assert_allclose(m[inner] - 1.0, pw[inner] * (xr[c] + f * (xr[c + 1] - xr[c]) - 1.0),
+                                   rtol=1e-12, atol=1e-15)
+
+
+def test_speckle_granular_term_closed_form():
+    """The granular term alone: with (Ag0, Ag1) = (1, 0) the multiplier is the
+    granular variate of index k itself (stream term 0), with (0, 1) it is
+    1 + zeta (xi_g(k) - 1)."""
+    S = 150
+    fan = O.Fan(3, S, 1.0, 0.2, 0.0, 9)
+    k = np.arange(S)
+    for ag0, ag1 in ((1.0, 0.0), (0.0, 1.0)):
+        ph = O.Physics(speckle_on=True, Ar=0.0, Ag0=ag0, Ag1=ag1, seed=77)
+        for j in (1, 2):
+            xg = _speckle_words(fan, ph, j, 0, S)
+            expect = 1.0 + (ag0 + ag1 * k / (S - 1)) * (xg - 1.0)
+            np.testing.assert_allclose(O.speckle_ray(fan, ph, j), expect, rtol=1e-14, atol=1e-15)
+
+
 def test_philox_uniformity_and_rayleigh_moments():
     key = [0x12345678, 0x9ABCDEF0]
     n = 1 << 15
