@@ -73,8 +73,9 @@ enum { DUS_ATTEN_IN_SYSTEM = 0, DUS_ATTEN_POST_HOC = 1, DUS_ATTEN_OFF = 2 };
 #define DUS_MAX_BLUR_RADIUS 32     /* ceil(3 * max(sigma0, sigma1)) */
 
 typedef struct {
-    int32_t nx, ny, nz;            /* voxels per axis, each >= 2; nx * ny * nz < 2^31,
-                                      nx * ny < 2^24 (else DUS_EUNSUPPORTED) */
+    int32_t nx, ny, nz;            /* voxels per axis, each >= 2, and nx * ny * nz < 2^31
+                                      (else DUS_ESHAPE); nx * ny < 2^24 and nz < 2^24
+                                      (else DUS_EUNSUPPORTED) */
     float spacing_mm[3];           /* > 0 */
     float origin_mm[3];            /* world position of voxel (0,0,0)'s centre */
 } dus_volume;
@@ -136,7 +137,14 @@ int dus_render_bmode(const float *Z, const dus_volume *vol, const float *poses,
                      void *stream);
 
 /*
- * Exact gradient of dus_render_bmode (hand-written adjoint).
+ * Exact gradient of dus_render_bmode (hand-written adjoint).  The paper
+ * builds the renderer to be differentiable so that B-mode losses can drive
+ * slice-to-volume registration (a gradient with respect to the probe pose)
+ * and volumetric reconstruction (a gradient with respect to the impedance
+ * volume): Sec. 1 and Sec. 4.  This call differentiates every step of
+ * Sec. 2.3-2.4 as dus_render_bmode computes it: the Eq. 1 coefficients of
+ * the trilinear samples, the depth-resolved solves of Eq. 2-4, the first
+ * differences, attenuation, speckle gains and the lateral blur.
  *   grad_bmode  device FP32, dL/d(bmode), same layout as bmode
  *   grad_Z      device FP32 [nz][ny][nx] or NULL: dL/dZ is ADDED (+=)
  *   grad_pose   device FP32 [n_poses][6] or NULL: dL/dpose, OVERWRITTEN
@@ -263,8 +271,15 @@ int dus_footprint_mask(const dus_volume *vol, const float *poses, const dus_fan 
 
 /*
  * Batched fused step: forward, loss = sum over poses of mean((I - target)^2),
- * adjoint.  A plan fixes the volume shape, the fans and the physics; each
- * dus_plan_step replays one captured HIP graph on `stream`.
+ * adjoint.  One step is one iteration of the gradient-based registration or
+ * reconstruction the paper names as the renderer's purpose (Sec. 1, Sec. 4):
+ * the B-modes of many probe poses are rendered as in Sec. 2.3-2.4 (Eq. 1-4,
+ * fan geometry, attenuation, speckle, blur), compared with target images,
+ * and the loss is differentiated with respect to the impedance volume and
+ * the poses (as dus_render_bmode_backward does).  The paper prints no loss;
+ * the mean squared error per pose is this library's choice.  A plan fixes
+ * the volume shape, the fans and the physics; each dus_plan_step replays one
+ * captured HIP graph on `stream`.
  */
 typedef struct dus_plan dus_plan;
 
@@ -289,6 +304,14 @@ typedef struct {
 int dus_set_schedule(const dus_schedule *sched);
 int dus_get_schedule(dus_schedule *sched);
 
+/*
+ * A plan for the fused step above: the volume record, the n_poses fan
+ * records and the physics (all HOST, copied into the plan) are validated as
+ * for dus_render_bmode, and flags is a combination of DUS_PLAN_*.  *out
+ * receives the plan (NULL on failure); the caller destroys it with
+ * dus_plan_destroy.  Creating a plan allocates host memory and one HIP
+ * stream for graph capture on the current device, never device memory.
+ */
 int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans,
                     int32_t n_poses, const dus_physics *phys, int32_t flags);
 /* The plan's workspace holds, besides the images of the step, what the
@@ -301,6 +324,11 @@ int64_t dus_plan_workspace_bytes(const dus_plan *plan);
 int dus_plan_set_schedule(dus_plan *plan, const dus_schedule *sched);
 int dus_plan_get_schedule(const dus_plan *plan, dus_schedule *sched);
 /*
+ * One fused step of the plan (Sec. 2.3-2.4 forward, MSE, adjoint; see above)
+ * on `stream`: the first call, and any call whose pointers or workspace size
+ * differ from the previous call's, captures a new HIP graph; the others
+ * replay it.  Z and poses as for dus_render_bmode; the workspace has at
+ * least dus_plan_workspace_bytes(plan) bytes, 256-byte aligned.
  *   target   device FP32, same layout as bmode
  *   bmode    device FP32 or NULL: the rendered image is also written
  *   loss     device FP64 scalar or NULL: receives the loss (overwritten)

@@ -48,9 +48,11 @@ int check_volume(const dus_volume *v)
     if (v->nx < 2 || v->ny < 2 || v->nz < 2) return fail(DUS_ESHAPE, "each volume axis needs >= 2 voxels");
     const long long n = (long long)v->nx * v->ny * v->nz;
     if (n >= (1ll << 31)) return fail(DUS_ESHAPE, "volume has 2^31 voxels or more");
-    // the kernels' flat voxel index uses 24-bit multiplies by the slice size
+    // the kernels' flat voxel index multiplies the slice index by the slice
+    // size with 24-bit multiplies: both operands must stay below 2^24
     if ((long long)v->nx * v->ny >= (1ll << 24))
         return fail(DUS_EUNSUPPORTED, "a volume slice (nx * ny) must hold fewer than 2^24 voxels");
+    if (v->nz >= (1 << 24)) return fail(DUS_EUNSUPPORTED, "a volume must have fewer than 2^24 slices (nz)");
     for (int a = 0; a < 3; ++a) {
         if (!finite_f(v->spacing_mm[a]) || !(v->spacing_mm[a] > 0.0f))
             return fail(DUS_EINVAL, "voxel spacing must be finite and > 0");

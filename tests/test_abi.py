@@ -105,6 +105,11 @@ def test_validation_errors():
     assert _render(bad, f, 1, p) == _lib.DUS_EUNSUPPORTED
     bad.nx, bad.ny, bad.nz = 4096, 4095, 2        # below 2^24 is accepted (validation only)
     assert L.dus_workspace_bytes(ctypes.byref(bad), f, 1, ctypes.byref(p), 0) >= 0
+    bad.nx, bad.ny, bad.nz = 2, 2, 1 << 24         # 2^24 slices: beyond the 24-bit slice index
+    assert _render(bad, f, 1, p) == _lib.DUS_EUNSUPPORTED
+    assert L.dus_workspace_bytes(ctypes.byref(bad), f, 1, ctypes.byref(p), 0) == _lib.DUS_EUNSUPPORTED
+    bad.nz = (1 << 24) - 1                          # the largest slice count accepted
+    assert L.dus_workspace_bytes(ctypes.byref(bad), f, 1, ctypes.byref(p), 0) >= 0
     bad = _vol()
     bad.spacing_mm = (ctypes.c_float * 3)(1.0, 0.0, 1.0)
     assert _render(bad, f, 1, p) == _lib.DUS_EINVAL
