@@ -319,7 +319,9 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans,
  * block (tile carries), (v0, v1, D) as 3 doubles per 4 samples (chunk
  * states), one FP32 gain per pixel (with speckle or post-hoc attenuation),
  * and 9 doubles of pose partials: about 10 B per ray-sample, on top of the
- * step's images (4 B per pixel each). */
+ * step's images (4 B per pixel each: the pre-blur image, the residual and
+ * its blur transpose with blur on, and the per-sample dL/dZ, which a
+ * DUS_PLAN_POSE_ONLY plan does not keep). */
 int64_t dus_plan_workspace_bytes(const dus_plan *plan);
 int dus_plan_set_schedule(dus_plan *plan, const dus_schedule *sched);
 int dus_plan_get_schedule(const dus_plan *plan, dus_schedule *sched);

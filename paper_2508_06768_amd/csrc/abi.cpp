@@ -220,9 +220,10 @@ struct WsLayout {
     size_t total = 0;
 };
 
-WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int mode)
+WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int mode, bool pose_only = false)
 {
-    // mode 0: forward, 1: backward, 2: plan step
+    // mode 0: forward, 1: backward, 2: plan step (pose_only: a plan that
+    // never scatters dL/dZ, so it keeps no per-sample dL/dZ)
     WsLayout L;
     const size_t img = (size_t)image_extent(fans, n_poses) * sizeof(float);
     size_t off = 0;
@@ -242,9 +243,11 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         off = align_up(off + img);
     }
     if (mode == 1 || mode == 2) {
-        L.zb = off;
-        L.zb_bytes = img;
-        off = align_up(off + img);
+        if (!(mode == 2 && pose_only)) {
+            L.zb = off;
+            L.zb_bytes = img;
+            off = align_up(off + img);
+        }
         L.acc = off;
         L.acc_bytes = (size_t)std::max(n_poses, 1) * dus::kPoseAcc * sizeof(double);
         off = align_up(off + L.acc_bytes);
@@ -446,7 +449,7 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
         int64_t r0 = 0;
         for (const auto &t : tabs) {
             DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, src, nullptr,
-                                         reinterpret_cast<float *>((char *)ws + L.zb), grad_Z,
+                                         grad_Z ? reinterpret_cast<float *>((char *)ws + L.zb) : nullptr, grad_Z,
                                          grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0, nullptr, nullptr,
                                          nullptr, nullptr, nullptr, st),
                     "adjoint kernel launch");
@@ -657,7 +660,7 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, 
     p->phys = *phys;
     p->flags = flags;
     p->tabs = build_tables(fans, n_poses);
-    p->ws = layout(fans, n_poses, phys, 2);
+    p->ws = layout(fans, n_poses, phys, 2, (flags & DUS_PLAN_POSE_ONLY) != 0);
     p->extent = image_extent(fans, n_poses);
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
@@ -735,8 +738,8 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     const int n_poses = (int)p->fans.size();
     double *acc = reinterpret_cast<double *>((char *)ws + p->ws.acc);
     double *rpart = reinterpret_cast<double *>((char *)ws + p->ws.rp);
-    float *zbar = reinterpret_cast<float *>((char *)ws + p->ws.zb);
     float *gZ = (p->flags & DUS_PLAN_POSE_ONLY) ? nullptr : grad_Z;
+    float *zbar = p->ws.zb_bytes ? reinterpret_cast<float *>((char *)ws + p->ws.zb) : nullptr;
     double *part = reinterpret_cast<double *>((char *)ws + p->ws.part);
     int64_t n_part = 0;
     const Sched &sc = p->sched;
@@ -782,7 +785,9 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     int64_t r0 = 0;        // rays of the tables before this one (pose partials)
     if (adj)
         for (const auto &t : p->tabs) {
-            DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, blur ? nullptr : target, zbar,
+            // dL/dZ per sample is stored only for the scatter
+            DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, blur ? nullptr : target,
+                                        gZ ? zbar : nullptr,
                                         grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0,
                                         (!blur && loss) ? part + n_part : nullptr,
                                         fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? cst : nullptr,

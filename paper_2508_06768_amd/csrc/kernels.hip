@@ -1232,7 +1232,8 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             const double ql = s_rho[pad8(i)];
             const double qr = (k + 1 < S) ? ((i + 1 < T) ? s_rho[pad8(i + 1)] : rbar_next) : 0.0;
             const double zb = fma(-qr, zr, ql * zl);
-            if (k < S) zbar[obase + k] = (float)zb;
+            // zbar is NULL when no volume gradient is wanted (nothing reads it)
+            if (zbar && k < S) zbar[obase + k] = (float)zb;
             if (pose_part) {
                 // dL/dp = zb dZ/dp; dL/dR accumulates (s_k dir) outer dL/dp
                 const double sk = fma((double)k, ray.ds, ray.r0);
@@ -2202,6 +2203,7 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
                           const float *poses, const float *zbar, float *gZ, hipStream_t st)
 {
     if (t.total_rays <= 0 || !gZ) return hipSuccess;
+    if (!zbar) return hipErrorInvalidValue;
     // 0: automatic.  Eight rays per wavefront, unless that leaves fewer than
     // two wavefronts per SIMD; then two (more wavefronts, each walking a
     // quarter as many groups)
