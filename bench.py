@@ -10,9 +10,10 @@ volume, cleared every step) and dL/dpose -- one captured HIP graph per step
 (the batched fused form).  Synthetic, seeded inputs.
 
 Printed: one JSON line with ray-samples/s of that step, the same for the
-plain per-pose form and the forward-only form, the roofline of the dominant
-kernel (HIP events on the launch stream) and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+plain per-pose form and the forward-only form, the uneven 64-pose batch
+(128-512 rays x 256-2048 samples per pose) in its batched and plain forms,
+the roofline of the dominant kernel (HIP events on the launch stream) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--poses B] [--gpus 1]
 """
@@ -30,7 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue roof: 256 CUs x 4 SIMDs, each issuing one wave64 instruction per
+# 4 cycles (16 lanes per cycle), at the 2.4 GHz peak clock; FP64 and
+# non-packed FP32 instructions issue at this rate alike
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "adjoint_hbm_traffic_64x256x1024.md")
+VALU_FILE = os.path.join(ROOT, "profiles", "instruction_mix_64x256x1024.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2508_06768_amd", "csrc", "kernels.hip")
 CALIB_BYTES = 512 << 20
 
@@ -52,13 +58,13 @@ def timed(fn, reps, stream_events):
     return start.elapsed_time(stop) / reps
 
 
-def measured_traffic():
-    """HBM bytes per adjoint launch from the committed rocprofv3 counter
-    summary, or None when the kernel source has changed since the counters
-    were taken (the summary records the SHA-256 of the kernel source)."""
+def profile_field(path, name):
+    """A number recorded in a committed rocprofv3 counter summary, or None
+    when the kernel source has changed since the counters were taken (each
+    summary records the SHA-256 of the kernel source it measured)."""
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
         src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -70,9 +76,14 @@ def measured_traffic():
     if fields.get("kernel_source_sha256") != src:
         return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[name])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per adjoint launch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return profile_field(TRAFFIC_FILE, "traffic_bytes_per_launch")
 
 
 def cpu_baseline(case, budget_s: float):
@@ -93,8 +104,7 @@ def cpu_baseline(case, budget_s: float):
         pose = case.poses[p].astype(np.float64)
         img = O.render(vol, pose, fans[p], ph)
         _, g = O.mse_loss_grad(img, np.zeros_like(img))     # the target does not change the cost
-        gv, gp = O.backward(vol, pose, fans[p], ph, g)
-        gV += gv
+        O.backward(vol, pose, fans[p], ph, g, grad_volume=gV)   # dL/dZ added into gV in place
         done += 1
         samples += fans[p].n_rays * fans[p].n_samples
         if time.perf_counter() - t0 >= budget_s:
@@ -130,6 +140,72 @@ def cpu_baseline(case, budget_s: float):
         O.render(v1, c1.poses[0].astype(np.float64), f1, p1, solver=solver)
         out[f"phantom_64x256_forward_{solver}_s"] = time.perf_counter() - t1
     return out
+
+
+def uneven_batch(Z, dev, reps: int, plain: bool, ev):
+    """The uneven 64-pose batch (128-512 rays x 256-2048 samples, 40-90 deg,
+    100-240 mm deep, speckle + blur) on the same volume: the fused step
+    (forward + MSE + adjoint with dL/dZ and dL/dpose) and the forward alone,
+    batched (one graph per step, one launch per kernel) and plain (one launch
+    sequence per pose, no graph), with ray-samples/s and the algorithmic
+    bytes as a share of the HBM peak."""
+    import torch
+
+    from paper_2508_06768_amd import synth
+    from paper_2508_06768_amd.render import FusedStep, Geometry, footprint_voxels, render
+
+    case = synth.case_batched()
+    geom = Geometry(case.Z.shape, case.spacing, case.origin, case.fans, case.phys)
+    poses = torch.from_numpy(case.poses).to(dev)
+    target = render(Z, torch.from_numpy(case.extra["target_poses"]).to(dev), geom).clone()
+    N = geom.total
+    vfp = footprint_voxels(poses, geom)
+    # forward: 4 B per pixel written + 4 B per footprint voxel read; step:
+    # 4 B per pixel of target read + 4 B (volume) + 8 B (dL/dZ read-modify-
+    # write) per footprint voxel
+    fwd_bytes, step_bytes = 4.0 * N + 4.0 * vfp, 4.0 * N + 12.0 * vfp
+    step = FusedStep(geom, zero_grad_z=True)
+    gZ = torch.zeros_like(Z)
+    gp = torch.empty((geom.n_poses, 6), device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    out = torch.empty(N, device=dev)
+    ws_f = geom.workspace(False, dev)
+
+    def rec(ms, nbytes):
+        return {"ms": ms, "value": N / (ms * 1e-3), "pct_hbm": 100.0 * nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+
+    fused = lambda: step.step(Z, poses, target, loss=loss, grad_Z=gZ, grad_pose=gp)  # noqa: E731
+    fused()
+    res = {"poses": geom.n_poses, "ray_samples_per_step": N, "footprint_voxels": vfp,
+           "fused_batched": rec(timed(fused, reps, ev), step_bytes)}
+    render(Z, poses, geom, out=out, ws=ws_f)
+    res["forward_batched"] = rec(timed(lambda: render(Z, poses, geom, out=out, ws=ws_f), reps, ev), fwd_bytes)
+    if plain:
+        singles = []
+        for p in range(geom.n_poses):
+            g1 = Geometry(case.Z.shape, case.spacing, case.origin, [case.fans[p]], case.phys)
+            o0, o1 = int(geom.offsets[p]), int(geom.offsets[p + 1])
+            singles.append((FusedStep(g1, zero_grad_z=False, graph=False), poses[p:p + 1].contiguous(),
+                            target[o0:o1], g1, out[o0:o1], g1.workspace(False, dev)))
+        gp1 = torch.empty((1, 6), device=dev)
+
+        def plain_step():
+            gZ.zero_()
+            for s1, p1, t1, *_ in singles:
+                s1.step(Z, p1, t1, loss=loss, grad_Z=gZ, grad_pose=gp1)
+
+        def plain_fwd():
+            for _, p1, _, g1, o1, w1 in singles:
+                render(Z, p1, g1, out=o1, ws=w1)
+
+        plain_step()
+        res["fused_plain"] = rec(timed(plain_step, max(2, reps // 4), ev), step_bytes)
+        plain_fwd()
+        res["forward_plain"] = rec(timed(plain_fwd, max(2, reps // 4), ev), fwd_bytes)
+        for s1, *_ in singles:
+            s1.close()
+    step.close()
+    return res
 
 
 def main():
@@ -267,6 +343,10 @@ def main():
              "scan_convert_512x512": {"ms": ms_scan}}
     log(f"bench: modes {json.dumps(modes)}")
 
+    log("bench: uneven 64-pose batch")
+    uneven = uneven_batch(Z, dev, max(5, args.steps // 2), not args.no_plain, ev)
+    log(f"bench: uneven batch {json.dumps(uneven)}")
+
     if args.calib_copy:
         src = torch.empty(CALIB_BYTES // 4, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -280,6 +360,23 @@ def main():
         log("bench: timing the FP64 CPU oracle")
         cpu = cpu_baseline(case, args.cpu_budget)
 
+    # roofline of the dominant kernel: algorithmic HBM bytes over its
+    # event-timed duration (frac is on HBM), and the VALU issue roof from
+    # the committed instruction counters (lane-operations = SQ_INSTS_VALU x
+    # 64 per launch), which decide the bound while they match the source
+    hbm_frac = kern[dom]["GBs"] / HBM_PEAK_GBS
+    lane_ops = profile_field(VALU_FILE, f"valu_lane_ops_per_launch_{dom}")
+    alu = None
+    if lane_ops is not None:
+        ach = lane_ops / (kern[dom]["ms"] * 1e-3)
+        alu = {"achieved": ach, "peak": VALU_PEAK_LANE_OPS, "unit": "lane-op/s", "frac": ach / VALU_PEAK_LANE_OPS,
+               "lane_ops_per_launch": lane_ops, "lane_ops_per_ray_sample": lane_ops / N}
+    bound = "alu" if alu is None or alu["frac"] > hbm_frac else "hbm"
+    # whole step: 4 B per pixel of target + 4 B (volume) + 8 B (dL/dZ
+    # read-modify-write) per footprint voxel; the full clear of dL/dZ
+    # (4 B per voxel) is reported beside it
+    step_bytes = 4.0 * N + 12.0 * vfp
+
     res = {
         "metric": "ray-samples/s, batched fused forward+MSE+adjoint (256^3 vol, 256 rays x 1024 samples/pose)",
         "value": value,
@@ -291,7 +388,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "fp32 volume, images and gradients; fp64 positions, samples and recurrence",
         "data": "synthetic",
         "config": {
             "workload": f"{B} poses x 256 rays x 1024 samples, 70 deg fans over a 256^3 1 mm brain-like "
@@ -299,6 +396,9 @@ def main():
                         "(dL/dZ full volume, dL/dpose), one HIP graph per step",
             "poses": B, "ray_samples_per_step": N, "footprint_voxels": vfp, "volume_voxels": n_vox,
         },
+        "step_alg_bytes": step_bytes,
+        "step_pct_hbm": 100.0 * step_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "step_pct_hbm_with_grad_clear": 100.0 * (step_bytes + 4.0 * n_vox) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "forward_batched": {"ms": ms_fwd, "value": N / (ms_fwd * 1e-3)},
         "plain_per_pose": None if plain_ms is None else {"ms": plain_ms, "value": N / (plain_ms * 1e-3)},
         "plain_forward_per_pose": (None if plain_fwd_ms is None
@@ -307,16 +407,19 @@ def main():
         "phases_ms": phases,
         "kernels": kern,
         "roofline": {
-            "bound": "hbm",
+            "bound": bound,
             "kernel": dom,
             "achieved": kern[dom]["GBs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": kern[dom]["GBs"] / HBM_PEAK_GBS,
+            "frac": hbm_frac,
+            "frac_of": "hbm",
             "traffic": measured_traffic() if dom == "adjoint" else None,
             "alg_bytes": kern[dom]["alg_bytes"],
             "ms": kern[dom]["ms"],
+            "alu": alu,
         },
+        "uneven_batch": uneven,
         "schedule": step.get_schedule(),
         "autotune_trials": None if tune is None else tune.get("trials"),
         "cpu_baseline": cpu,

@@ -61,10 +61,9 @@ def oracle_backward(case: synth.Case, grad_flat: np.ndarray, poses=None, want_vo
     for p, f in enumerate(case.fans):
         n = f.n_rays * f.n_samples
         pose = np.asarray(poses[p], dtype=np.float32).astype(np.float64)
-        g, gpp = O.backward(vol, pose, oracle_fan(f), ph, grad_flat[off:off + n].astype(np.float64),
-                            want_volume=want_volume)
-        if want_volume:
-            gV += g
+        # the oracle adds each pose's dL/dZ into gV in place
+        _, gpp = O.backward(vol, pose, oracle_fan(f), ph, grad_flat[off:off + n].astype(np.float64),
+                            want_volume=want_volume, grad_volume=gV)
         gp[p] = gpp
         off += n
     return gV, gp
@@ -75,6 +74,17 @@ def rel_l2(a, b) -> float:
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a - b))
+
+
+def grad_report(gpu, ref) -> dict:
+    """Volume-gradient parity: relative l2 over the volume, and the largest
+    voxel error over the largest |reference| voxel."""
+    gpu = np.asarray(gpu, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
+    m = np.abs(ref).max() if ref.size else 0.0
+    d = np.abs(gpu - ref)
+    return {"rel_l2": rel_l2(gpu, ref),
+            "max_abs_over_max": float(d.max() / m) if m > 0 else float(d.max() if d.size else 0.0)}
 
 
 def parity_report(gpu, ref, fans=None) -> dict:

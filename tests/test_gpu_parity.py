@@ -3,7 +3,8 @@
 Bars:
   forward images      per-image relative l2 <= 1e-5, and every pixel within
                       1e-5 of the image's max |value|
-  adjoint             dL/dZ relative l2 <= 1e-5 over the volume; dL/dpose per
+  adjoint             dL/dZ relative l2 <= 1e-5 over the volume, and every
+                      voxel within 1e-5 of max |dL/dZ|; dL/dpose per
                       component within 1e-5 * ||dL/dpose||
   speckle generator   Philox words bit-exact
 """
@@ -61,6 +62,27 @@ def _check_images(gpu, ref, tag, fans=None):
     print(tag, rep, flush=True)
     assert rep["rel_l2"] <= RTOL_IMG, rep
     assert rep["max_abs_over_max"] <= RTOL_IMG, rep
+
+
+def check_grad_volume(gZ, rV, tag):
+    """dL/dZ against the oracle: relative l2 over the volume and the largest
+    voxel error over the largest |dL/dZ| (the elementwise bar)."""
+    rep = H.grad_report(gZ, rV)
+    print(tag, "dZ", rep, flush=True)
+    assert rep["rel_l2"] <= RTOL_GRAD, rep
+    assert rep["max_abs_over_max"] <= RTOL_GRAD, rep
+
+
+def check_grad_pose(gp, rp, tag):
+    """Every pose's gradient: each component within 1e-5 of the norm of the
+    oracle's gradient of that pose."""
+    worst = 0.0
+    for p in range(len(rp)):
+        nrm = np.linalg.norm(rp[p])
+        err = float(np.abs(gp[p] - rp[p]).max())
+        worst = max(worst, err / nrm if nrm > 0 else err)
+        assert np.all(np.abs(gp[p] - rp[p]) <= RTOL_GRAD * nrm + 1e-30), (tag, p, gp[p], rp[p])
+    print(tag, "pose worst |error| / |gradient|", worst, flush=True)
 
 
 # --------------------------------------------------------------------------
@@ -138,20 +160,13 @@ def test_backward_parity_ragged(refl, effects):
     w = rng.standard_normal(geom.total).astype(np.float32)
     gZ, gp = render_backward(Z, poses, geom, torch.from_numpy(w).to(DEV))
     rV, rp = H.oracle_backward(case, w.astype(np.float64))
-    gZ = gZ.cpu().numpy()
-    gp = gp.cpu().numpy()
-    e = H.rel_l2(gZ, rV)
-    print("dZ rel l2", e, flush=True)
-    assert e <= RTOL_GRAD
-    for p in range(len(case.fans)):
-        nrm = np.linalg.norm(rp[p])
-        print("pose", p, gp[p], rp[p], flush=True)
-        assert np.all(np.abs(gp[p] - rp[p]) <= RTOL_GRAD * nrm + 1e-30)
+    check_grad_volume(gZ.cpu().numpy(), rV, f"backward {refl} fx={effects}")
+    check_grad_pose(gp.cpu().numpy(), rp, f"backward {refl} fx={effects}")
 
 
-def _plan_reference(case, target):
-    """Oracle image, MSE loss (mean per fan, summed over fans), dL/dZ and
-    dL/dpose of the fused step."""
+def _plan_reference(case, target, want_volume=True):
+    """Oracle image, MSE loss (mean per fan, summed over fans), dL/dZ (None
+    without want_volume) and dL/dpose of the fused step."""
     img = H.oracle_render(case)
     tf = target.astype(np.float32).astype(np.float64)
     ref_loss = 0.0
@@ -165,23 +180,24 @@ def _plan_reference(case, target):
         ref_loss += np.mean(d * d)
         grad[off:off + n] = 2 * d / n
         off += n
-    rV, rp = H.oracle_backward(case, grad)
+    rV, rp = H.oracle_backward(case, grad, want_volume=want_volume)
     return img, ref_loss, rV, rp
 
 
-def _run_plan(case, target, schedule=None, replays=3, image=True):
+def _run_plan(case, target, schedule=None, replays=3, image=True, pose_only=False):
     from paper_2508_06768_amd.render import FusedStep
     geom, Z, poses = _gpu(case)
     T = torch.from_numpy(target.astype(np.float32)).to(DEV)
-    step = FusedStep(geom, zero_grad_z=True, schedule=schedule)
+    step = FusedStep(geom, zero_grad_z=not pose_only, pose_only=pose_only, schedule=schedule)
     bm = torch.empty(geom.total, device=DEV) if image else None
     loss = torch.zeros(1, dtype=torch.float64, device=DEV)
-    gZ = torch.full_like(Z, 123.0)
+    gZ = None if pose_only else torch.full_like(Z, 123.0)
     gp = torch.empty((geom.n_poses, 6), device=DEV)
     for _ in range(replays):                    # replays of the same graph
         step.step(Z, poses, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
     torch.cuda.synchronize()
-    out = (bm.cpu().numpy() if image else None, loss.item(), gZ.cpu().numpy(), gp.cpu().numpy())
+    out = (bm.cpu().numpy() if image else None, loss.item(), None if gZ is None else gZ.cpu().numpy(),
+           gp.cpu().numpy())
     step.close()
     return out
 
@@ -191,12 +207,11 @@ def _check_plan(case, got, ref, tag):
     img, ref_loss, rV, rp = ref
     if bm is not None:
         _check_images(bm, img, f"{tag} image", case.fans)
+    print(tag, "loss", loss, ref_loss, flush=True)
     assert loss == pytest.approx(ref_loss, rel=1e-5)
-    e = H.rel_l2(gZ, rV)
-    print(tag, "dZ rel l2", e, flush=True)
-    assert e <= RTOL_GRAD
-    for p in range(len(case.fans)):
-        assert np.all(np.abs(gp[p] - rp[p]) <= RTOL_GRAD * np.linalg.norm(rp[p]) + 1e-30)
+    if rV is not None:
+        check_grad_volume(gZ, rV, tag)
+    check_grad_pose(gp, rp, tag)
 
 
 def test_fused_plan_matches_oracle():
@@ -238,10 +253,8 @@ def test_plan_with_two_fan_tables():
         w = rng.standard_normal(geom.total).astype(np.float32)
         gZ, gp = render_backward(Zt, Pt, geom, torch.from_numpy(w).to(DEV))
         rV, rp = H.oracle_backward(case, w.astype(np.float64))
-        assert H.rel_l2(gZ.cpu().numpy(), rV) <= RTOL_GRAD
-        gpn = gp.cpu().numpy()
-        for q in range(P):
-            assert np.all(np.abs(gpn[q] - rp[q]) <= RTOL_GRAD * np.linalg.norm(rp[q]) + 1e-30)
+        check_grad_volume(gZ.cpu().numpy(), rV, f"70 fans backward fx={effects}")
+        check_grad_pose(gp.cpu().numpy(), rp, f"70 fans backward fx={effects}")
 
 
 def rough_column_case(refl, effects, seed=13) -> synth.Case:

@@ -18,6 +18,7 @@ import pytest
 from oracle import oracle as O
 from paper_2508_06768_amd import synth
 from tests import helpers as H
+from tests.test_gpu_parity import _check_plan, _plan_reference, _run_plan, check_grad_pose, check_grad_volume
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -55,10 +56,9 @@ def test_adjoint_full_size_vs_oracle_and_finite_differences():
     # FP64 oracle adjoint with its own image
     _, g_or = O.mse_loss_grad(ref, tf)
     rV, rp = H.oracle_backward(case, g_or)
-    e = H.rel_l2(gZ, rV)
-    print("dZ vs oracle adjoint", e, "pose", gp, rp[0], flush=True)
-    assert e <= 1e-5
-    assert np.all(np.abs(gp - rp[0]) <= 1e-5 * np.linalg.norm(rp[0]))
+    print("pose", gp, rp[0], flush=True)
+    check_grad_volume(gZ, rV, "adjoint 512 x 1024")
+    check_grad_pose(gp[None], rp, "adjoint 512 x 1024")
     # finite differences of the oracle's forward
     vol = H.oracle_volume(case)
     fan = H.oracle_fan(case.fans[0])
@@ -81,7 +81,7 @@ def test_adjoint_full_size_vs_oracle_and_finite_differences():
     assert np.all(g_sel[64:] == 0.0)
     assert np.all(fd[64:] == 0.0)
     assert np.linalg.norm(g_sel[:64] - fd[:64]) <= 1e-3 * np.linalg.norm(fd[:64])
-    assert np.all(err <= 1e-2)
+    assert np.all(err <= 1e-3)
     fdp = O.fd_pose(vol, pose, fan, ph, tf2, h_t=2e-7, h_w=2e-9, richardson=True)
     print("pose FD", fdp, "gpu", gp, flush=True)
     assert np.all(np.abs(gp - fdp) <= 1e-3 * np.abs(fdp))
@@ -123,6 +123,49 @@ def test_batched_equals_plain_and_oracle():
         assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
 
 
+def test_uneven_batch_fused_step_vs_oracle():
+    """The uneven 64-pose batch (128-512 rays x 256-2048 samples, 40-90 deg,
+    100-240 mm deep, speckle and blur) as one fused forward + MSE + adjoint
+    step replayed from its graph: all 64 images, the loss, dL/dZ over the
+    volume and all 64 pose gradients against the FP64 oracle, whose target
+    is its own render at the +-5 mm / +-5 deg offset poses."""
+    case = synth.case_batched()
+    print("case", case.name, "ray-samples", case.ray_samples, flush=True)
+    target = H.oracle_render(case, poses=case.extra["target_poses"])
+    got = _run_plan(case, target, replays=2)
+    print("GPU step done", flush=True)
+    _check_plan(case, got, _plan_reference(case, target), "uneven batch")
+
+
+def registration_shape_case(n_poses=4, n=320):
+    """Fans of the registration workload (384 rays x 1536 samples, 70 deg,
+    192 mm deep, ds = 0.125 mm) on a volume of 0.5 mm voxels, noise smoothed
+    over 4 voxels, speckle and blur: a 320^3 crop of the 512^3 volume's
+    extent (160 mm), so part of every ray runs past the volume; apexes and
+    tilts drawn as for the registration poses; targets +-1 mm / +-1 deg
+    away."""
+    h = 0.5
+    Z = synth.brain_volume(1005, n, h, noise_sigma_vox=4.0)
+    rng = np.random.default_rng(1005)
+    gt = synth.random_poses(rng, n_poses, (n - 1) * h)
+    init = synth.offset_poses(rng, gt, 1.0, 1.0)
+    fans = [synth.FanSpec(384, 1536, 70 * synth.DEG, 192.0 / 1536, 0.0, p) for p in range(n_poses)]
+    return synth.Case(f"registration_shape_{n}cube", Z, (h,) * 3, (0.0,) * 3, init, fans,
+                      synth.effects_physics(1005), extra={"gt_poses": gt})
+
+
+def test_pose_only_step_vs_oracle_registration_shape():
+    """The pose-only fused step (no dL/dZ, as registration runs it) at the
+    registration fans' shape: images, loss and every pose gradient against
+    the FP64 oracle."""
+    case = registration_shape_case()
+    print("case", case.name, "ray-samples", case.ray_samples, flush=True)
+    target = H.oracle_render(case, poses=case.extra["gt_poses"])
+    got = _run_plan(case, target, replays=2, pose_only=True)
+    assert got[2] is None
+    _check_plan(case, got, _plan_reference(case, target, want_volume=False), "pose-only 384 x 1536")
+
+
 @pytest.mark.parametrize("schedule", [None, {"fwd_chunk": 16, "bwd_chunk": 4, "xcd_group": 16, "scatter_rays": 8}])
 def test_bench_workload_full_size(schedule):
     """The benchmark's own step at its full size: 64 poses x 256 rays x 1024
@@ -161,13 +204,8 @@ def test_bench_workload_full_size(schedule):
     print("loss", loss.item(), ref_loss, flush=True)
     assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
     rV, rp = H.oracle_backward(case, grad)
-    e = H.rel_l2(gZ.cpu().numpy(), rV)
-    print("dZ rel l2", e, flush=True)
-    assert e <= 1e-5
-    gpn = gp.cpu().numpy()
-    worst = max(float(np.abs(gpn[p] - rp[p]).max() / np.linalg.norm(rp[p])) for p in range(len(case.fans)))
-    print("pose worst |error| / |gradient|", worst, flush=True)
-    assert worst <= 1e-5
+    check_grad_volume(gZ.cpu().numpy(), rV, "bench step")
+    check_grad_pose(gp.cpu().numpy(), rp, "bench step")
     step.close()
 
 
@@ -285,11 +323,12 @@ def test_edge_sizes():
         gZ, gp = render_backward(Zt, P, geom, torch.from_numpy(w).to(DEV))
         rV, rp = H.oracle_backward(case, w.astype(np.float64))
         if np.abs(rV).max() > 0:
-            assert H.rel_l2(gZ.cpu().numpy(), rV) <= 1e-5
-        for p in range(len(fans)):
-            assert np.all(np.abs(gp.cpu().numpy()[p] - rp[p]) <= 1e-5 * np.linalg.norm(rp[p]) + 1e-30)
+            check_grad_volume(gZ.cpu().numpy(), rV, "edge")
+        check_grad_pose(gp.cpu().numpy(), rp, "edge")
         target = H.oracle_render(case, poses=case.poses + np.float32([[0.3, -0.2, 0.1, 0.0, 0.0, 0.0]]))
         _check_plan(case, _run_plan(case, target, replays=2), _plan_reference(case, target), "edge plan")
+        _check_plan(case, _run_plan(case, target, replays=2, pose_only=True),
+                    _plan_reference(case, target, want_volume=False), "edge pose-only plan")
 
 
 def test_registration_loop():
@@ -329,9 +368,16 @@ def test_registration_loop():
     _, gp_ref = render_backward(Zt, P, geom, grad.float(), want_Z=False)
     torch.cuda.synchronize()
     assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
+    # the two GPU paths form the residual from the same FP32 image but round
+    # it differently (FP32 in the step, FP64 here): agreement to 1e-4 of the
+    # largest component; the step itself is held to the oracle below
     np.testing.assert_allclose(gp.cpu().numpy(), gp_ref.cpu().numpy(), rtol=1e-4,
                                atol=1e-5 * float(gp_ref.abs().max()))
     step.close()
+    case = synth.Case("registration96", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), init, fans, ph)
+    target = H.oracle_render(case, poses=gt)
+    _check_plan(case, _run_plan(case, target, replays=2, pose_only=True),
+                _plan_reference(case, target, want_volume=False), "registration96 pose-only")
     res = register(Zt, geom, T, P, steps=80, lr_t=0.2, lr_w=math.radians(0.2))
     print("registration loss", res.loss_history[0], "->", res.loss_history[-1], "steps/s", res.steps_per_s,
           flush=True)
