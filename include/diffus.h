@@ -87,7 +87,8 @@ typedef struct {
     float ds_mm;                   /* depth step, > 0 */
     float r0_mm;                   /* apex-to-first-sample distance, finite */
     int32_t speckle_id;            /* speckle stream of this fan (counter word 2) */
-    int64_t out_offset;            /* element offset of this pose's image */
+    int64_t out_offset;            /* element offset of this pose's image, >= 0;
+                                      out_offset + n_rays * n_samples <= 2^48 */
 } dus_fan;
 
 typedef struct {

@@ -41,6 +41,7 @@ constexpr int kDefaultFwdChunk = 8;
 constexpr int kDefaultBwdChunk = 4;
 constexpr int kDefaultXcdGroup = 16;
 constexpr int kDefaultScatterRays = 0;     // automatic (launch_scatter)
+constexpr int64_t kMaxImageExtent = (int64_t)1 << 48;   // image elements addressed by out_offset
 
 int check_volume(const dus_volume *v)
 {
@@ -103,6 +104,9 @@ int check_fans(const dus_fan *fans, int32_t n_poses)
             return fail(DUS_EINVAL, "fan geometry must be finite with ds > 0");
         if (f.out_offset < 0) return fail(DUS_ESHAPE, "out_offset < 0");
         const int64_t n = (int64_t)f.n_rays * f.n_samples;
+        // image offsets and workspace sizes (several bytes per element)
+        // must not overflow
+        if (f.out_offset > kMaxImageExtent - n) return fail(DUS_ESHAPE, "out_offset + n_rays * n_samples exceeds 2^48");
         if (n > 0) spans.push_back({f.out_offset, f.out_offset + n});
     }
     std::sort(spans.begin(), spans.end());
