@@ -159,6 +159,26 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
                               void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * dus_render_bmode_backward for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, with the workspace taken
+ * from a static device array of DUS_STATIC_SCRATCH_BYTES per GPU instead of
+ * a caller buffer.  The caller still passes every input and output.  The
+ * call allocates nothing: the array is part of the library's code object,
+ * and each GPU that runs the library holds its own copy until the process
+ * ends (its address is looked up on the first call on each device).
+ * Returns DUS_EUNSUPPORTED when dus_workspace_bytes(..., 1) exceeds
+ * DUS_STATIC_SCRATCH_BYTES.  Every call on one GPU shares that GPU's array,
+ * which keeps the last call's contents (each call overwrites what it
+ * reads): calls that overlap on one GPU (on different streams, or from
+ * different threads) race and must be serialised by the caller.
+ */
+#define DUS_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+int dus_render_bmode_backward_static(const float *Z, const dus_volume *vol, const float *poses,
+                                     const dus_fan *fans, int32_t n_poses, const dus_physics *phys,
+                                     const float *grad_bmode, float *grad_Z, float *grad_pose, void *stream);
+
+/*
  * Philox4x32-10 (Salmon et al., SC'11), the generator of the speckle
  * multipliers (Sec. 2.4).  counters: device uint32 [n][4]; out: device
  * uint32 [n][4]; key = (seed low 32 bits, seed high 32 bits).

@@ -22,6 +22,7 @@ PLAN_POSE_ONLY, PLAN_ZERO_GRAD_Z, PLAN_NO_GRAPH = 1, 2, 4
 # phases of a plan step (DUS_PHASE_*), in launch order
 PHASES = ("clear", "forward", "blur_loss", "adjoint", "scatter", "finish")
 MAX_SAMPLES, MAX_RAYS, MAX_BLUR_RADIUS = 16384, 65536, 32
+STATIC_SCRATCH_BYTES = 32 << 20
 
 
 class DusVolume(ctypes.Structure):
@@ -70,6 +71,9 @@ SIGNATURES = {
     "dus_render_bmode_backward": (ctypes.c_int, [c_vp, ctypes.POINTER(DusVolume), c_vp,
                                                  ctypes.POINTER(DusFan), c_i32, ctypes.POINTER(DusPhysics),
                                                  c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "dus_render_bmode_backward_static": (ctypes.c_int, [c_vp, ctypes.POINTER(DusVolume), c_vp,
+                                                        ctypes.POINTER(DusFan), c_i32, ctypes.POINTER(DusPhysics),
+                                                        c_vp, c_vp, c_vp, c_vp]),
     "dus_philox4x32_10": (ctypes.c_int, [c_vp, c_i64, c_u64, c_vp, c_vp]),
     "dus_pixel_gain": (ctypes.c_int, [ctypes.POINTER(DusFan), ctypes.POINTER(DusPhysics), c_vp, c_vp]),
     "dus_sample_volume": (ctypes.c_int, [c_vp, ctypes.POINTER(DusVolume), c_vp, ctypes.POINTER(DusFan), c_i32,

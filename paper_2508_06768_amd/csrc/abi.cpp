@@ -471,6 +471,26 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
     return DUS_OK;
 }
 
+int dus_render_bmode_backward_static(const float *Z, const dus_volume *vol, const float *poses,
+                                     const dus_fan *fans, int32_t n_poses, const dus_physics *phys,
+                                     const float *grad_bmode, float *grad_Z, float *grad_pose, void *stream)
+{
+    static_assert(DUS_STATIC_SCRATCH_BYTES == dus::kStaticScratchBytes, "static scratch size");
+    int s;
+    if ((s = check_common(Z, vol, poses, fans, n_poses, phys)) != DUS_OK) return s;
+    const WsLayout L = layout(fans, n_poses, phys, 1);
+    if (L.total > dus::kStaticScratchBytes) {
+        char msg[160];
+        snprintf(msg, sizeof(msg), "this call needs %zu bytes of scratch; the static scratch holds %zu",
+                 L.total, dus::kStaticScratchBytes);
+        return fail(DUS_EUNSUPPORTED, msg);
+    }
+    void *ws = nullptr;
+    if (L.total > 0) DUS_HIP(dus::static_scratch(&ws), "static scratch address");
+    return dus_render_bmode_backward(Z, vol, poses, fans, n_poses, phys, grad_bmode, grad_Z, grad_pose, ws,
+                                     ws ? dus::kStaticScratchBytes : 0, stream);
+}
+
 int dus_philox4x32_10(const uint32_t *counters, int64_t n, uint64_t seed, uint32_t *out, void *stream)
 {
     if (n < 0) return fail(DUS_ESHAPE, "n < 0");

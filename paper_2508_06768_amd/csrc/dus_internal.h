@@ -160,4 +160,10 @@ hipError_t launch_map_backward(const float *in, int64_t n, const LutArgs &lut, c
                                double *grad_z, hipStream_t st);
 hipError_t launch_pixel_gain(const PhysArgs &p, const FanRec &f, float *out, hipStream_t st);
 
+// Static device scratch of the allocation-free entry points (a file-scope
+// __device__ array of kernels.hip): *ptr receives its device address on the
+// current device, looked up on the first call per device.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+hipError_t static_scratch(void **ptr);
+
 }  // namespace dus

@@ -33,6 +33,7 @@
 // are reduced per ray in FP64.
 #include <algorithm>
 #include <math.h>
+#include <mutex>
 #include <stdint.h>
 
 #include "../../include/diffus.h"
@@ -2292,6 +2293,41 @@ hipError_t launch_blur_residual(const PhysArgs &p, const FanTable &t, const floa
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_blur(true, p, t, resid, ebar, st);
+}
+
+// --------------------------------------------------------------------------
+// Static device scratch of the allocation-free entry points.  The array is
+// part of the code object: every GPU that loads the library holds its own
+// copy, at its own address, until the process ends.  In host code its name
+// stands for the host-side shadow, not for device memory, so the device
+// address is looked up once per device (with that device current) and only
+// that address is handed to kernels.
+// --------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void **ptr)
+{
+    *ptr = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_pose_finalize(const double *acc, const float *poses, int n_poses,

@@ -174,6 +174,23 @@ def render_backward(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, grad_b
     return gZ, gp
 
 
+def render_backward_static(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, grad_bmode: torch.Tensor,
+                           grad_Z: torch.Tensor | None = None, grad_pose: torch.Tensor | None = None) -> None:
+    """The adjoint with the library's static device scratch instead of a
+    workspace (``dus_render_bmode_backward_static``): the library allocates
+    nothing.  The caller passes the outputs: grad_Z (FP32, +=) and/or
+    grad_pose (FP32 [n_poses, 6], overwritten); either may be None."""
+    _check_inputs(Z, poses, geom)
+    dev = Z.device
+    _check_buffer(grad_bmode, "grad_bmode", geom.total, device=dev)
+    _check_buffer(grad_Z, "grad_Z", Z.numel(), device=dev)
+    _check_buffer(grad_pose, "grad_pose", 6 * geom.n_poses, device=dev)
+    check(_lib.lib().dus_render_bmode_backward_static(_ptr(Z), ctypes.byref(geom.vol_c), _ptr(poses), geom.fans_c,
+                                                      geom.n_poses, ctypes.byref(geom.phys_c), _ptr(grad_bmode),
+                                                      _ptr(grad_Z), _ptr(grad_pose), _stream()),
+          "dus_render_bmode_backward_static")
+
+
 class RenderBmode(torch.autograd.Function):
     """bmode = render(Z, poses); gradients from the hand-written adjoint."""
 

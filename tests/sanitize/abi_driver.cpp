@@ -109,6 +109,10 @@ int main()
                                                  dev<float>(kImg), nullptr, dev<float>(kGrad + 0x100000),
                                                  dev<void>(kWs), (size_t)wsb, nullptr) == DUS_OK,
                        "backward pose only");
+                expect(dus_render_bmode_backward_static(dev<float>(kZ), &v, dev<float>(kPoses), f.data(), nf, &p,
+                                                        dev<float>(kImg), dev<float>(kGrad),
+                                                        dev<float>(kGrad + 0x100000), nullptr) == DUS_OK,
+                       "backward, static scratch");
                 for (int flags : {0, (int)DUS_PLAN_POSE_ONLY, (int)DUS_PLAN_ZERO_GRAD_Z, (int)DUS_PLAN_NO_GRAPH,
                                   (int)(DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH)}) {
                     dus_plan *plan = nullptr;
@@ -174,6 +178,10 @@ int main()
     expect(dus_workspace_bytes(&v, f.data(), 2, &q, 0) == DUS_EINVAL, "huge cell");
     dus_plan *plan = reinterpret_cast<dus_plan *>(1);
     expect(dus_plan_create(&plan, &v, f.data(), 2, &p, 1 << 10) == DUS_EINVAL && plan == nullptr, "plan flag");
+    std::vector<dus_fan> big = fans(1, 4096, 2048);          // 8 M ray-samples: beyond the static scratch
+    expect(dus_render_bmode_backward_static(dev<float>(kZ), &v, dev<float>(kPoses), big.data(), 1, &p,
+                                            dev<float>(kImg), dev<float>(kGrad), nullptr, nullptr) == DUS_EUNSUPPORTED,
+           "static scratch too small");
     expect(g_launches == before, "nothing launched on invalid requests");
 
     // the smaller entry points

@@ -202,4 +202,9 @@ hipError_t launch_map_backward(const float *, int64_t, const LutArgs &, const fl
     return hipSuccess;
 }
 hipError_t launch_pixel_gain(const PhysArgs &, const FanRec &, float *, hipStream_t) { return hipSuccess; }
+hipError_t static_scratch(void **ptr)
+{
+    *ptr = reinterpret_cast<void *>((uintptr_t)0x7000000);     // 256-byte aligned, never dereferenced
+    return hipSuccess;
+}
 }  // namespace dus
