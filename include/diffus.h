@@ -364,7 +364,8 @@ int dus_plan_step(dus_plan *plan, const float *Z, const float *poses, const floa
 
 /*
  * Phases of a plan step, in launch order (measurement and tracing):
- *   CLEAR      fill kernels for the pose accumulators and grad_Z
+ *   CLEAR      fill kernel for the pose accumulators and grad_Z, when the
+ *              forward kernel does not run (else its wavefronts clear them)
  *   FORWARD    forward kernel (pixels, tile carries, per-pixel gains)
  *   BLUR_LOSS  blur, MSE residual and loss partials, blur transpose (blur on)
  *   ADJOINT    adjoint scan kernel (dL/dZ per sample, pose sums; with blur

@@ -42,6 +42,7 @@ constexpr int kDefaultBwdChunk = 4;
 constexpr int kDefaultXcdGroup = 16;
 constexpr int kDefaultScatterRays = 0;     // automatic (launch_scatter)
 constexpr int64_t kMaxImageExtent = (int64_t)1 << 48;   // image elements addressed by out_offset
+constexpr int kFusedBlurRadius = 8;        // launch_blur_residual runs in one pass up to this radius
 
 int check_volume(const dus_volume *v)
 {
@@ -221,6 +222,7 @@ struct WsLayout {
     size_t cex = 0, cex_bytes = 0;     // tile-carry exponents, one int32 per record
     size_t cst = 0, cst_bytes = 0;     // chunk states, kStateDoubles doubles per record
     size_t gain = 0, gain_bytes = 0;   // per-pixel gains recorded by the forward (plan step)
+    size_t rays = 0, rays_bytes = 0;   // ray geometry the adjoint hands the scatter, one RayRec per ray
     size_t total = 0;
 };
 
@@ -241,7 +243,9 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         L.eb_bytes = img;
         off = align_up(off + img);
     }
-    if (p->blur_on && mode == 2) {
+    // the plan keeps the MSE residual in memory only for blur radii above
+    // the one-pass kernel's bound (8 rays)
+    if (p->blur_on && mode == 2 && ceilf(3.0f * std::max(p->blur_sigma0, p->blur_sigma1)) > (float)kFusedBlurRadius) {
         L.res = off;
         L.res_bytes = img;
         off = align_up(off + img);
@@ -261,6 +265,11 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         L.rp = off;
         L.rp_bytes = rays * dus::kRayPart * sizeof(double);
         off = align_up(off + L.rp_bytes);
+        if (!(mode == 2 && pose_only)) {
+            L.rays = off;
+            L.rays_bytes = rays * sizeof(dus::RayRec);
+            off = align_up(off + L.rays_bytes);
+        }
     }
     if (mode == 2) {
         // one partial per blur block or per ray of every table
@@ -340,15 +349,20 @@ int make_sched(const dus_schedule *sc, Sched &n)
     return DUS_OK;
 }
 
+// zero: buffers the first forward launch clears besides rendering
 int enqueue_forward(const Sched &sc, const dus::VolArgs &va, const dus::PhysArgs &pa,
                     const std::vector<dus::FanTable> &tabs, const float *poses, float *out,
                     float *min_pivot, hipStream_t st, double *carry = nullptr, int32_t *carry_exp = nullptr,
-                    double *cstate = nullptr, float *gain = nullptr)
+                    double *cstate = nullptr, float *gain = nullptr, const dus::ZeroArgs &zero = dus::ZeroArgs{})
 {
-    for (const auto &t : tabs)
+    bool first = true;
+    for (const auto &t : tabs) {
+        if (t.total_rays <= 0) continue;
         DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, out, min_pivot, 0, carry,
-                                    carry_exp, cstate, gain, st),
+                                    carry_exp, cstate, gain, st, first ? zero : dus::ZeroArgs{}),
                 "forward kernel launch");
+        first = false;
+    }
     return DUS_OK;
 }
 
@@ -452,7 +466,8 @@ int dus_render_bmode_backward(const float *Z, const dus_volume *vol, const float
         double *rpart = reinterpret_cast<double *>((char *)ws + L.rp);
         int64_t r0 = 0;
         for (const auto &t : tabs) {
-            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses, src, nullptr,
+            DUS_HIP(dus::launch_backward(sc.bwd_chunk, sc.xcd_group, sc.scatter_rays, va, pa, t, poses,
+                                         reinterpret_cast<dus::RayRec *>((char *)ws + L.rays) + r0, src, nullptr,
                                          grad_Z ? reinterpret_cast<float *>((char *)ws + L.zb) : nullptr, grad_Z,
                                          grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0, nullptr, nullptr,
                                          nullptr, nullptr, nullptr, st),
@@ -764,6 +779,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     double *rpart = reinterpret_cast<double *>((char *)ws + p->ws.rp);
     float *gZ = (p->flags & DUS_PLAN_POSE_ONLY) ? nullptr : grad_Z;
     float *zbar = p->ws.zb_bytes ? reinterpret_cast<float *>((char *)ws + p->ws.zb) : nullptr;
+    dus::RayRec *rays = p->ws.rays_bytes ? reinterpret_cast<dus::RayRec *>((char *)ws + p->ws.rays) : nullptr;
     double *part = reinterpret_cast<double *>((char *)ws + p->ws.part);
     int64_t n_part = 0;
     const Sched &sc = p->sched;
@@ -775,25 +791,29 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     float *gain = p->ws.gain_bytes ? reinterpret_cast<float *>((char *)ws + p->ws.gain) : nullptr;
     const bool blur = p->phys.blur_on != 0;
     const bool fwd = blur || bmode;               // the forward kernel runs
+    // the pose accumulators and dL/dZ are cleared by the forward kernel's
+    // wavefronts (when it runs and renders something), else by a fill kernel
+    dus::ZeroArgs zero{};
+    zero.a = gZ;
+    zero.na = (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z)) ? (int64_t)p->vol.nx * p->vol.ny * p->vol.nz : 0;
+    zero.b = acc;
+    zero.nb = grad_pose ? (int64_t)n_poses * dus::kPoseAcc : 0;
+    const bool fwd_clears = fwd && p->extent > 0;
     DUS_HIP(mark(DUS_PHASE_CLEAR), "event");
-    {
-        // the pose accumulators and dL/dZ cleared in one launch
-        const int64_t na = (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z)) ? (int64_t)p->vol.nx * p->vol.ny * p->vol.nz : 0;
-        const int64_t nb = grad_pose ? (int64_t)n_poses * dus::kPoseAcc : 0;
-        DUS_HIP(dus::launch_zero_pair(gZ, na, acc, nb, st), "zero kernel");
-    }
+    if (!fwd_clears) DUS_HIP(dus::launch_zero_pair(zero.a, zero.na, zero.b, zero.nb, st), "zero kernel");
     DUS_HIP(mark(DUS_PHASE_FORWARD), "event");
     if (fwd) {
         int s;
         float *img = blur ? reinterpret_cast<float *>((char *)ws + p->ws.pre) : bmode;
-        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, img, nullptr, st, car, cex, cst, gain)) != DUS_OK)
+        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, img, nullptr, st, car, cex, cst, gain,
+                                 fwd_clears ? zero : dus::ZeroArgs{})) != DUS_OK)
             return s;
     }
     DUS_HIP(mark(DUS_PHASE_BLUR_LOSS), "event");
     const float *eb = nullptr;
     if (blur) {
         const float *pre = reinterpret_cast<float *>((char *)ws + p->ws.pre);
-        float *res = reinterpret_cast<float *>((char *)ws + p->ws.res);
+        float *res = p->ws.res_bytes ? reinterpret_cast<float *>((char *)ws + p->ws.res) : nullptr;
         float *ebw = reinterpret_cast<float *>((char *)ws + p->ws.eb);
         for (const auto &t : p->tabs) {
             DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, ebw, loss ? part + n_part : nullptr, st),
@@ -810,7 +830,8 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     if (adj)
         for (const auto &t : p->tabs) {
             // dL/dZ per sample is stored only for the scatter
-            DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, eb, blur ? nullptr : target,
+            DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, gZ ? rays + r0 : nullptr, eb,
+                                        blur ? nullptr : target,
                                         gZ ? zbar : nullptr,
                                         grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0,
                                         (!blur && loss) ? part + n_part : nullptr,
@@ -821,9 +842,13 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
             r0 += t.total_rays;
         }
     DUS_HIP(mark(DUS_PHASE_SCATTER), "event");
-    if (adj && gZ)
-        for (const auto &t : p->tabs)
-            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, poses, zbar, gZ, st), "scatter kernel");
+    if (adj && gZ) {
+        r0 = 0;
+        for (const auto &t : p->tabs) {
+            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, rays + r0, zbar, gZ, st), "scatter kernel");
+            r0 += t.total_rays;
+        }
+    }
     DUS_HIP(mark(DUS_PHASE_FINISH), "event");
     if (adj && grad_pose) {
         r0 = 0;

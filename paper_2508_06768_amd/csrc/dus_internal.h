@@ -53,6 +53,14 @@ struct FanTable {
     FanRec f[kMaxFans];
 };
 
+// A ray's geometry, written by the adjoint kernel (which sets it up from the
+// pose and the fan) for the dL/dZ scatter: sample k sits at voxel coordinate
+// u0 + k du.
+struct RayRec {
+    double u0[3], du[3];
+};
+static_assert(sizeof(RayRec) == 48, "RayRec layout");
+
 struct VolArgs {
     const float *Z;
     int32_t nx, ny, nz, pad_;
@@ -82,16 +90,28 @@ constexpr int kRayPart = 9;
 // carry / carry_exp: optional tile-carry records (4 doubles / 1 int each);
 // cstate: optional chunk states (kStateDoubles per carry record; needs carry);
 // gain: optional per-pixel gain (speckle x post-hoc attenuation) output
+// Buffers a kernel clears on the side (a[0..na) and b[0..nb) set to zero)
+struct ZeroArgs {
+    float *a;
+    long long na;
+    double *b;
+    long long nb;
+};
+
+// zero: cleared by the forward's wavefronts besides their rays (the fused
+// step's dL/dZ and pose accumulators), or {} for none
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out,
                           float *min_pivot, int pivot_base, double *carry, int32_t *carry_exp,
-                          double *cstate, float *gain, hipStream_t st);
+                          double *cstate, float *gain, hipStream_t st, const ZeroArgs &zero = ZeroArgs{});
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
 // the fused form (target given) loss receives one partial per ray.  With
 // pose_acc (a flag here), pose_part receives kRayPart doubles per ray of the
 // table; launch_pose_reduce then adds them into the pose accumulators.
+// rays: one RayRec per ray of the table, written by the adjoint when zbar is
+// (the scatter reads them)
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
-                           const PhysArgs &p, const FanTable &t, const float *poses,
+                           const PhysArgs &p, const FanTable &t, const float *poses, RayRec *rays,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
                            double *pose_acc, double *pose_part, double *loss, const double *carry,
                            const int32_t *carry_exp, const double *cstate, const float *gain,
@@ -99,7 +119,7 @@ hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const Vol
 // the two halves of launch_backward: the adjoint scan (dL/dZ per sample into
 // zbar, pose sums, fused loss partials) and the scatter of zbar into gZ
 hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
-                          const FanTable &t, const float *poses, const float *gsrc,
+                          const FanTable &t, const float *poses, RayRec *rays, const float *gsrc,
                           const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
                           const float *gain, hipStream_t st);
@@ -107,7 +127,7 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
 // per fan (fixed order)
 hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double *pose_acc, hipStream_t st);
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
-                          const float *poses, const float *zbar, float *gZ, hipStream_t st);
+                          const RayRec *rays, const float *zbar, float *gZ, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st);
 // image = B pre (optional), ebar = B^T (2 (image - target) / P); loss

@@ -634,7 +634,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
                                                 int pivot_base, double *__restrict__ carry,
                                                 int32_t *__restrict__ carry_exp,
                                                 double *__restrict__ cstate,
-                                                float *__restrict__ gain_out, int xgrp)
+                                                float *__restrict__ gain_out, int xgrp, ZeroArgs zero)
 {
     constexpr int T = 64 * C;
     static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
@@ -646,6 +646,21 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     __shared__ float s_xir[SPK ? T / 4 + 8 : 1];
 
     const int lane = threadIdx.x;
+    if (zero.na > 0 || zero.nb > 0) {
+        // the step's clears, spread over the forward's wavefronts: the stores
+        // drain while the wavefront renders its ray
+        const long long stride = (long long)gridDim.x * 64;
+        const long long i0 = (long long)blockIdx.x * 64 + lane;
+        if ((reinterpret_cast<uintptr_t>(zero.a) & 15) == 0) {
+            float4 *a4 = reinterpret_cast<float4 *>(zero.a);
+            const long long n4 = zero.na / 4;
+            for (long long i = i0; i < n4; i += stride) a4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (long long i = 4 * n4 + i0; i < zero.na; i += stride) zero.a[i] = 0.0f;
+        } else {
+            for (long long i = i0; i < zero.na; i += stride) zero.a[i] = 0.0f;
+        }
+        for (long long i = i0; i < zero.nb; i += stride) zero.b[i] = 0.0;
+    }
     const int g = remap_block(blockIdx.x, gridDim.x, xgrp);
     const int fi = find_fan(tab, g);
     const FanRec fr = tab.f[fi];
@@ -849,6 +864,7 @@ __device__ __forceinline__ Adj adj_step(const Adj &a, double v0, double v1, doub
 template <int C, bool SPK, bool FUSED>
 __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable tab,
                                                  const float *__restrict__ poses,
+                                                 RayRec *__restrict__ rays_out,
                                                  const float *__restrict__ gsrc,
                                                  const float *__restrict__ target,
                                                  float *__restrict__ zbar,
@@ -885,6 +901,16 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     if (S <= 0) return;
     Ray ray;
     setup_ray(v, p, fr, poses, j, ray);
+    if (rays_out && lane == 0) {
+        // the ray's geometry for the scatter
+        RayRec r;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.u0[a] = ray.u0[a];
+            r.du[a] = ray.du[a];
+        }
+        rays_out[g] = r;
+    }
     const bool absm = (p.refl == 0);
     const double sgn = absm ? 1.0 : -1.0;
     const double a2 = ray.a2;
@@ -1303,7 +1329,7 @@ struct ScatterBox {
 };
 
 template <int RB>
-__global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const float *__restrict__ poses,
+__global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const RayRec *__restrict__ rays,
                                                 const float *__restrict__ zbar, float *__restrict__ gZ,
                                                 int seg, int xgrp)
 {
@@ -1335,10 +1361,16 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const f
     const int k_begin = blockIdx.y * seg;
     if (k_begin >= S) return;                   // whole wavefront: segment past this fan's depth
     const int k_end = min(S, k_begin + seg);
-    PhysArgs p{};
-    p.atten = 2;
+    // RB rays per wavefront, their geometry as the adjoint set it up
     Ray ray;
-    setup_ray(v, p, fr, poses, ray_ok ? j : 0, ray, false);     // RB rays per wavefront
+    {
+        const RayRec &r = rays[fr.ray_begin + (ray_ok ? j : 0)];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ray.u0[a] = r.u0[a];
+            ray.du[a] = r.du[a];
+        }
+    }
     const float *zrow = zbar + fr.out_offset + (long long)(ray_ok ? j : 0) * S;
     const int sxy = v.nx * v.ny;
     for (int t = lane; t < CAP; t += 64) s_box[t] = 0.0;
@@ -1632,6 +1664,115 @@ __global__ __launch_bounds__(256) void k_blur(PhysArgs p, FanTable tab, const fl
         }
     }
     if (MODE == 2 && loss_acc) {
+        // one partial per block, summed by k_sum_f64 (no contended atomics)
+        __shared__ double s_part[4];
+        lsum = wave_sum(lsum) * inv_npix;
+        if (lane == 0) s_part[wv] = lsum;
+        __syncthreads();
+        if (tid == 0) loss_acc[b] = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+    }
+}
+
+// Residual and transpose blur in one pass (the fused step with blur, radius
+// bound RM <= 8): ebar = B^T (2 (B pre - target) / P), image = B pre
+// (optional), one loss partial per block.  A block of 4 wavefronts takes 64
+// rays x 64 depths as k_blur does.  It first forms the residual of its rays
+// and of RM rays on either side (each wavefront RW of those 64 + 2 RM rows,
+// from a register window of pre, as MODE 2), parks it in LDS (zero outside
+// the fan, as MODE 1 reads it), and then applies B^T to its own rows from
+// LDS, as MODE 1.  The arithmetic of each value is that of the two-kernel
+// path; only the loss partials group the rows differently.  The residual
+// never goes to memory.
+template <int RM>
+__global__ __launch_bounds__(256) void k_blur_fused(PhysArgs p, FanTable tab, const float *__restrict__ pre,
+                                                    const float *__restrict__ target, float *__restrict__ ebar,
+                                                    float *__restrict__ image, double *__restrict__ loss_acc)
+{
+    constexpr int NR = kBlurRays + 2 * RM;     // residual rows J0 - RM .. J0 + 64 + RM - 1
+    constexpr int RW = NR / 4;                 // residual rows per wavefront
+    constexpr int W = RW + 2 * RM;             // pre window of a wavefront
+    static_assert(NR % 4 == 0, "residual rows split over four wavefronts");
+    __shared__ float s_r[NR][65];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int b = blockIdx.x;
+    const int fi = find_blur_fan(tab, b);
+    const FanRec fr = tab.f[fi];
+    const int S = fr.n_samples, n = fr.n_rays;
+    const int nkb = (S + 63) / 64;
+    const int lb = b - fr.blk_begin;
+    const int kb = lb % nkb, jb = lb / nkb;
+    const int k = kb * 64 + lane;
+    const int J0 = jb * kBlurRays;
+    const bool kin = k < S;
+    const long long col = fr.out_offset + min(k, S - 1);
+    const double inv_npix = 1.0 / ((double)n * (double)S);
+    const float two_inv_npix = (float)(2.0 * inv_npix);
+    float w[RM + 1];
+    const int r = blur_weights<RM>(p, S, min(k, S - 1), w);
+    double lsum = 0.0;
+    {
+        // residual rows g0 .. g0 + RW - 1 of this wavefront
+        const int g0 = J0 - RM + wv * RW;
+        float x[W];
+#pragma unroll
+        for (int m = 0; m < W; ++m) {
+            const int g = g0 - RM + m;
+            x[m] = pre[col + (long long)min(max(g, 0), n - 1) * S];
+        }
+        float tg[RW];
+#pragma unroll
+        for (int o = 0; o < RW; ++o) tg[o] = target[col + (long long)min(max(g0 + o, 0), n - 1) * S];
+#pragma unroll
+        for (int o = 0; o < RW; ++o) {
+            const int g = g0 + o;
+            float acc = 0.0f;
+#pragma unroll
+            for (int t = -RM; t <= RM; ++t) acc = fmaf(w[t < 0 ? -t : t], x[o + RM + t], acc);
+            const float d = acc - tg[o];
+            const bool in_fan = kin && g >= 0 && g < n;
+            s_r[wv * RW + o][lane] = in_fan ? d * two_inv_npix : 0.0f;
+            // the block's own rows: image and loss
+            if (in_fan && g >= J0 && g < J0 + kBlurRays) {
+                if (image) image[col + (long long)g * S] = acc;
+                lsum += (double)(d * d);
+            }
+        }
+    }
+    __syncthreads();
+    // transpose blur of this wavefront's 16 rays from the LDS residual
+    const int j0 = J0 + wv * kBlurRows;
+    if (kin && j0 < n) {
+        float tl[RM + 2];
+        {
+            float acc = 0.0f;
+            tl[RM + 1] = 0.0f;
+#pragma unroll
+            for (int t = RM; t >= 0; --t) {
+                if (t <= r) acc += w[t];
+                tl[t] = (t <= r) ? acc : 0.0f;
+            }
+        }
+        float x[kBlurRows + 2 * RM];
+#pragma unroll
+        for (int m = 0; m < kBlurRows + 2 * RM; ++m) x[m] = s_r[wv * kBlurRows + m][lane];
+#pragma unroll
+        for (int o = 0; o < kBlurRows; ++o) {
+            const int j = j0 + o;
+            if (j >= n) break;
+            float acc = 0.0f;
+#pragma unroll
+            for (int t = -RM; t <= RM; ++t) acc = fmaf(w[t < 0 ? -t : t], x[o + RM + t], acc);
+            if (j == 0 || j == n - 1) {
+                const float mult = (j == 0 && j == n - 1) ? 2.0f : 1.0f;
+                float e = 0.0f;
+#pragma unroll
+                for (int t = -RM; t <= RM; ++t) e = fmaf(tl[(t < 0 ? -t : t) + 1], x[o + RM + t], e);
+                acc = fmaf(mult, e, acc);
+            }
+            ebar[col + (long long)j * S] = acc;
+        }
+    }
+    if (loss_acc) {
         // one partial per block, summed by k_sum_f64 (no contended atomics)
         __shared__ double s_part[4];
         lsum = wave_sum(lsum) * inv_npix;
@@ -2131,18 +2272,18 @@ inline int grid_for(long long n, int block)
             hipLaunchKernelGGL((k_forward<CH, true>), dim3(grid), dim3(64), 0, st, v, p, t,    \
                                poses, out, min_pivot, pivot_base, carry, carry_exp, cstate,    \
                                gain,                                                           \
-                               xcd_group);                                                     \
+                               xcd_group, zero);                                               \
         else                                                                                   \
             hipLaunchKernelGGL((k_forward<CH, false>), dim3(grid), dim3(64), 0, st, v, p, t,   \
                                poses, out, min_pivot, pivot_base, carry, carry_exp, cstate,    \
                                gain,                                                           \
-                               xcd_group);                                                     \
+                               xcd_group, zero);                                               \
         break;
 
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out, float *min_pivot,
                           int pivot_base, double *carry, int32_t *carry_exp, double *cstate, float *gain,
-                          hipStream_t st)
+                          hipStream_t st, const ZeroArgs &zero)
 {
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
@@ -2158,7 +2299,7 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 
 #define DUS_BWD_LAUNCH(CH, SPK, FUSED)                                                          \
     hipLaunchKernelGGL((k_backward<CH, SPK, FUSED>), dim3(grid), dim3(64), 0, st, v, p, t,      \
-                       poses, gsrc, target, zbar, pose_acc ? pose_part : nullptr, loss, carry,           \
+                       poses, zbar ? rays : nullptr, gsrc, target, zbar, pose_acc ? pose_part : nullptr, loss, carry,           \
                        carry_exp, cstate, gain, xcd_group)
 
 #define DUS_BWD_CASE(CH)                                                                       \
@@ -2173,7 +2314,7 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
         break;
 
 hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
-                          const FanTable &t, const float *poses, const float *gsrc,
+                          const FanTable &t, const float *poses, RayRec *rays, const float *gsrc,
                           const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
                           const float *gain, hipStream_t st)
@@ -2181,6 +2322,7 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
     const int grid = t.total_rays;
     if (grid <= 0) return hipSuccess;
     if (pose_acc && !pose_part) return hipErrorInvalidValue;
+    if (zbar && !rays) return hipErrorInvalidValue;
     const bool fused = (target != nullptr);
     const bool spk = p.speckle && !gain;      // recorded gains replace the speckle variates
     if (!carry) cstate = nullptr;             // chunk states are read in the frames of the carry records
@@ -2201,10 +2343,10 @@ hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double
 }
 
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
-                          const float *poses, const float *zbar, float *gZ, hipStream_t st)
+                          const RayRec *rays, const float *zbar, float *gZ, hipStream_t st)
 {
     if (t.total_rays <= 0 || !gZ) return hipSuccess;
-    if (!zbar) return hipErrorInvalidValue;
+    if (!zbar || !rays) return hipErrorInvalidValue;
     // 0: automatic.  Eight rays per wavefront, unless that leaves fewer than
     // two wavefronts per SIMD; then two (more wavefronts, each walking a
     // quarter as many groups)
@@ -2215,22 +2357,23 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
         smax = std::max(smax, t.f[f].n_samples);
     }
     if (blocks <= 0 || smax <= 0) return hipSuccess;
-    // depth segments: enough wavefronts to fill the GPU (>= 8192), each
-    // segment a whole number of groups
+    // depth segments: about 32 wavefronts per SIMD over the launch (a
+    // wavefront's set-up is a few loads, so short segments cost little and
+    // even out the finishing times), each segment a whole number of groups
     const int G = 256 / scatter_rays;
     const int ngroups = (smax + G - 1) / G;
-    const int nseg = std::max(1, std::min(ngroups, (8192 + blocks - 1) / blocks));
+    const int nseg = std::max(1, std::min(ngroups, (32768 + blocks - 1) / blocks));
     const int seg = ((ngroups + nseg - 1) / nseg) * G;
     const dim3 grid(blocks, (smax + seg - 1) / seg);
     switch (scatter_rays) {
     case 2:
-        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, t, poses, zbar, gZ, seg, xcd_group);
+        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group);
         break;
     case 4:
-        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, t, poses, zbar, gZ, seg, xcd_group);
+        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group);
         break;
     case 8:
-        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, t, poses, zbar, gZ, seg, xcd_group);
+        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group);
         break;
     default:
         return hipErrorInvalidValue;
@@ -2239,16 +2382,16 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
 }
 
 hipError_t launch_backward(int chunk, int xcd_group, int scatter_rays, const VolArgs &v,
-                           const PhysArgs &p, const FanTable &t, const float *poses,
+                           const PhysArgs &p, const FanTable &t, const float *poses, RayRec *rays,
                            const float *gsrc, const float *target, float *zbar, float *gZ,
                            double *pose_acc, double *pose_part, double *loss, const double *carry,
                            const int32_t *carry_exp, const double *cstate, const float *gain,
                            hipStream_t st)
 {
-    hipError_t e = launch_adjoint(chunk, xcd_group, v, p, t, poses, gsrc, target, zbar, pose_acc, pose_part, loss,
-                                  carry, carry_exp, cstate, gain, st);
+    hipError_t e = launch_adjoint(chunk, xcd_group, v, p, t, poses, rays, gsrc, target, zbar, pose_acc, pose_part,
+                                  loss, carry, carry_exp, cstate, gain, st);
     if (e != hipSuccess) return e;
-    return launch_scatter(scatter_rays, xcd_group, v, t, poses, zbar, gZ, st);
+    return launch_scatter(scatter_rays, xcd_group, v, t, rays, zbar, gZ, st);
 }
 
 #define DUS_BLUR_LAUNCH(MODE, TGT, IMG, LOSS)                                                       \
@@ -2285,6 +2428,16 @@ hipError_t launch_blur_residual(const PhysArgs &p, const FanTable &t, const floa
     if (grid <= 0) return hipSuccess;
     const int R = p.blur_rmax;
     if (R > DUS_MAX_BLUR_RADIUS) return hipErrorInvalidValue;
+    // radius up to 8: one pass, the residual kept in LDS
+    if (R <= 4) {
+        hipLaunchKernelGGL((k_blur_fused<4>), dim3(grid), dim3(256), 0, st, p, t, pre, target, ebar, image, loss);
+        return hipGetLastError();
+    }
+    if (R <= 8) {
+        hipLaunchKernelGGL((k_blur_fused<8>), dim3(grid), dim3(256), 0, st, p, t, pre, target, ebar, image, loss);
+        return hipGetLastError();
+    }
+    if (!resid) return hipErrorInvalidValue;
     {
         const float *in = pre;
         float *out = resid;

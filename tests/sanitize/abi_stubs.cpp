@@ -119,19 +119,19 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t)
 
 namespace dus {
 hipError_t launch_forward(int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *, float *,
-                          float *, int, double *, int32_t *, double *, float *, hipStream_t)
+                          float *, int, double *, int32_t *, double *, float *, hipStream_t, const ZeroArgs &)
 {
     check_table(t);
     return hipSuccess;
 }
-hipError_t launch_backward(int, int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *,
+hipError_t launch_backward(int, int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *, RayRec *,
                            const float *, const float *, float *, float *, double *, double *, double *,
                            const double *, const int32_t *, const double *, const float *, hipStream_t)
 {
     check_table(t);
     return hipSuccess;
 }
-hipError_t launch_adjoint(int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *,
+hipError_t launch_adjoint(int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *, RayRec *,
                           const float *, const float *, float *, double *, double *, double *, const double *,
                           const int32_t *, const double *, const float *, hipStream_t)
 {
@@ -143,7 +143,7 @@ hipError_t launch_pose_reduce(const FanTable &t, const double *, double *, hipSt
     check_table(t);
     return hipSuccess;
 }
-hipError_t launch_scatter(int, int, const VolArgs &, const FanTable &t, const float *, const float *, float *,
+hipError_t launch_scatter(int, int, const VolArgs &, const FanTable &t, const RayRec *, const float *, float *,
                           hipStream_t)
 {
     check_table(t);
