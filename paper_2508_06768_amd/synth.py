@@ -281,6 +281,25 @@ def case_batched_c2(B: int = 64, seed: int = 1006, vol_seed: int = 1002) -> Case
                 effects_physics(seed), extra={"target_poses": tgt})
 
 
+def case_skewed(even: bool = False, seed: int = 1007, vol_seed: int = 1002, P: int = 64) -> Case:
+    """A batch whose ray lengths are very uneven: P - 1 poses of 256 rays x
+    256 samples and one pose of 64 rays x 16384 samples (the longest rays the
+    renderer takes), all 70 deg fans 200 mm deep, speckle and blur.  With
+    even=True the same number of ray-samples is spread over P fans of 256 rays
+    x 316 samples instead (the reference for the skewed batch's time)."""
+    Z = brain256(vol_seed)
+    rng = np.random.default_rng(seed)
+    poses = random_poses(rng, P, 255.0)
+    if even:
+        fans = [FanSpec(256, 316, 70 * DEG, 200.0 / 316, 0.0, p) for p in range(P)]
+    else:
+        fans = [FanSpec(256, 256, 70 * DEG, 200.0 / 256, 0.0, p) for p in range(P - 1)]
+        fans.append(FanSpec(64, 16384, 70 * DEG, 200.0 / 16384, 0.0, P - 1))
+    tgt = offset_poses(rng, poses, 5.0, 5.0)
+    return Case("skewed_even" if even else "skewed", Z, (1.0,) * 3, (0.0,) * 3, poses, fans,
+                effects_physics(seed), extra={"target_poses": tgt})
+
+
 def case_registration(seed: int = 1005, n: int = 512, P: int = 32, offset: float = 10.0) -> Case:
     """512^3 volume at 0.5 mm (noise sigma 4 voxels), 32 ground-truth poses,
     initial poses +-offset mm / +-offset deg (10 by default), 384 rays x 1536

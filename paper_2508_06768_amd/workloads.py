@@ -9,6 +9,10 @@
   512 x 1024;
 * ``batched_256cube_64poses``: the uneven 64-pose batch, forward + MSE +
   adjoint, one launch sequence per pose against one graph-replayed step;
+* ``skewed`` / ``skewed_even``: a batched step whose ray lengths are very
+  uneven (63 fans of 256 x 256 and one of 64 x 16384 samples) against the
+  same ray-samples spread evenly (64 fans of 256 x 316): the cost of rays
+  that are each walked by one wavefront from end to end;
 * ``table_R_rays_S_samples``: single renders at the shapes of the paper's
   timing tables (Sec. 3.4, Tables 2-3: 64-256 rays, 32-200 samples, one
   voxel per sample) on the 256^3 volume with speckle and blur;
@@ -144,6 +148,8 @@ def main(argv=None) -> None:
     case = synth.case_batched()
     fused(case, dev, per_pose=True)
     fused(case, dev, per_pose=False)
+    fused(synth.case_skewed(), dev, per_pose=False)
+    fused(synth.case_skewed(even=True), dev, per_pose=False)
     mapping(dev)
     if not args.skip_table:
         table_shapes(dev)
