@@ -307,7 +307,11 @@ typedef struct dus_plan dus_plan;
 enum {
     DUS_PLAN_POSE_ONLY = 1,   /* grad_Z is neither needed nor touched */
     DUS_PLAN_ZERO_GRAD_Z = 2, /* the step clears grad_Z itself (fill kernel) */
-    DUS_PLAN_NO_GRAPH = 4     /* launch eagerly instead of replaying a graph */
+    DUS_PLAN_NO_GRAPH = 4,    /* launch eagerly instead of replaying a graph */
+    DUS_PLAN_DETERMINISTIC = 8 /* dL/dZ bit-identical from step to step: summed as 64-bit fixed
+                                  point (scale 2^e set per step from the sum of |dL/dZ| over all
+                                  samples, so no sum can overflow) and rounded once to FP32,
+                                  instead of FP32 atomics; costs 8 B per voxel of workspace */
 };
 
 /* Ray-to-wavefront schedule; 0 fields select the library default. */

@@ -223,10 +223,13 @@ struct WsLayout {
     size_t cst = 0, cst_bytes = 0;     // chunk states, kStateDoubles doubles per record
     size_t gain = 0, gain_bytes = 0;   // per-pixel gains recorded by the forward (plan step)
     size_t rays = 0, rays_bytes = 0;   // ray geometry the adjoint hands the scatter, one RayRec per ray
+    size_t fix = 0, fix_bytes = 0;     // deterministic plan: 64-bit fixed-point dL/dZ per voxel
+    size_t fsc = 0, fsc_bytes = 0;     // its scale (2^e, 2^-e, the bound) and the bound's partials
     size_t total = 0;
 };
 
-WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int mode, bool pose_only = false)
+WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int mode, bool pose_only = false,
+                int64_t det_voxels = 0)
 {
     // mode 0: forward, 1: backward, 2: plan step (pose_only: a plan that
     // never scatters dL/dZ, so it keeps no per-sample dL/dZ)
@@ -297,6 +300,16 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
             L.gain_bytes = img;
             off = align_up(off + img);
         }
+    }
+    if (mode == 2 && det_voxels > 0 && !pose_only) {
+        L.fix = off;
+        L.fix_bytes = (size_t)det_voxels * sizeof(unsigned long long);
+        off = align_up(off + L.fix_bytes);
+        L.fsc = off;
+        size_t rays = 0;
+        for (const auto &t : build_tables(fans, n_poses)) rays += (size_t)t.total_rays;
+        L.fsc_bytes = (4 + rays) * sizeof(double);
+        off = align_up(off + L.fsc_bytes);
     }
     L.total = off;
     return L;
@@ -690,7 +703,7 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, 
     if ((s = check_volume(vol)) != DUS_OK) return s;
     if ((s = check_physics(phys)) != DUS_OK) return s;
     if ((s = check_fans(fans, n_poses)) != DUS_OK) return s;
-    if (flags & ~(DUS_PLAN_POSE_ONLY | DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH))
+    if (flags & ~(DUS_PLAN_POSE_ONLY | DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH | DUS_PLAN_DETERMINISTIC))
         return fail(DUS_EINVAL, "unknown plan flag");
     dus_plan *p = new (std::nothrow) dus_plan();
     if (!p) return fail(DUS_EINVAL, "out of host memory");
@@ -699,7 +712,8 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, 
     p->phys = *phys;
     p->flags = flags;
     p->tabs = build_tables(fans, n_poses);
-    p->ws = layout(fans, n_poses, phys, 2, (flags & DUS_PLAN_POSE_ONLY) != 0);
+    p->ws = layout(fans, n_poses, phys, 2, (flags & DUS_PLAN_POSE_ONLY) != 0,
+                   (flags & DUS_PLAN_DETERMINISTIC) ? (int64_t)vol->nx * vol->ny * vol->nz : 0);
     p->extent = image_extent(fans, n_poses);
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
@@ -793,9 +807,20 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     const bool fwd = blur || bmode;               // the forward kernel runs
     // the pose accumulators and dL/dZ are cleared by the forward kernel's
     // wavefronts (when it runs and renders something), else by a fill kernel
+    const int64_t n_vox = (int64_t)p->vol.nx * p->vol.ny * p->vol.nz;
+    // deterministic plan: dL/dZ is summed in the fixed-point buffer (cleared
+    // every step) and written into grad_Z at the end
+    unsigned long long *fix = (gZ && p->ws.fix_bytes) ? reinterpret_cast<unsigned long long *>((char *)ws + p->ws.fix)
+                                                      : nullptr;
+    double *fsc = fix ? reinterpret_cast<double *>((char *)ws + p->ws.fsc) : nullptr;
     dus::ZeroArgs zero{};
-    zero.a = gZ;
-    zero.na = (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z)) ? (int64_t)p->vol.nx * p->vol.ny * p->vol.nz : 0;
+    if (fix) {
+        zero.a = reinterpret_cast<float *>(fix);
+        zero.na = 2 * n_vox;
+    } else {
+        zero.a = gZ;
+        zero.na = (gZ && (p->flags & DUS_PLAN_ZERO_GRAD_Z)) ? n_vox : 0;
+    }
     zero.b = acc;
     zero.nb = grad_pose ? (int64_t)n_poses * dus::kPoseAcc : 0;
     const bool fwd_clears = fwd && p->extent > 0;
@@ -843,11 +868,23 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         }
     DUS_HIP(mark(DUS_PHASE_SCATTER), "event");
     if (adj && gZ) {
+        if (fix) {
+            r0 = 0;
+            for (const auto &t : p->tabs) {
+                DUS_HIP(dus::launch_abs_rows(t, zbar, fsc + 4 + r0, st), "fixed-point bound kernel");
+                r0 += t.total_rays;
+            }
+            DUS_HIP(dus::launch_fix_scale(fsc + 4, r0, fsc, st), "fixed-point scale kernel");
+        }
         r0 = 0;
         for (const auto &t : p->tabs) {
-            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, rays + r0, zbar, gZ, st), "scatter kernel");
+            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, rays + r0, zbar, gZ, st, fix, fsc),
+                    "scatter kernel");
             r0 += t.total_rays;
         }
+        if (fix)
+            DUS_HIP(dus::launch_fix_to_f32(fix, n_vox, fsc, gZ, (p->flags & DUS_PLAN_ZERO_GRAD_Z) != 0, st),
+                    "fixed-point conversion kernel");
     }
     DUS_HIP(mark(DUS_PHASE_FINISH), "event");
     if (adj && grad_pose) {

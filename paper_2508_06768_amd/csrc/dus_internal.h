@@ -126,8 +126,19 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
 // pose_acc[pose] += the sum of the table's per-ray partials, one wavefront
 // per fan (fixed order)
 hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double *pose_acc, hipStream_t st);
+// fix (nullable): deterministic mode, 64-bit fixed-point sums at the scale
+// fscale[0] (launch_fix_scale) instead of FP32 atomics into gZ
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
-                          const RayRec *rays, const float *zbar, float *gZ, hipStream_t st);
+                          const RayRec *rays, const float *zbar, float *gZ, hipStream_t st,
+                          unsigned long long *fix = nullptr, const double *fscale = nullptr);
+// deterministic dL/dZ: part[r] = the sum of |zbar| along the table's ray r
+// (one double per ray); fscale[2] = the sum of part[0..n), fscale[0..1] =
+// 2^e and 2^-e from it; the conversion of the fixed-point sums into gZ
+// (overwritten or added)
+hipError_t launch_abs_rows(const FanTable &t, const float *zbar, double *part, hipStream_t st);
+hipError_t launch_fix_scale(const double *part, int64_t n, double *fscale, hipStream_t st);
+hipError_t launch_fix_to_f32(const unsigned long long *fix, int64_t n, const double *fscale, float *gZ,
+                             bool overwrite, hipStream_t st);
 hipError_t launch_blur(bool transpose, const PhysArgs &p, const FanTable &t, const float *in,
                        float *out, hipStream_t st);
 // image = B pre (optional), ebar = B^T (2 (image - target) / P); loss

@@ -1321,7 +1321,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
 // FP64 sum of a voxel's FP32 contributions is rounded to FP32 once, when the
 // box is flushed.
 // --------------------------------------------------------------------------
-constexpr int kScatterSpl = 4;     // consecutive depths per lane
+constexpr int kScatterSpl = 4;     // consecutive depths per lane, at most
 
 template <int RB>
 struct ScatterBox {
@@ -1331,10 +1331,10 @@ struct ScatterBox {
 template <int RB>
 __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const RayRec *__restrict__ rays,
                                                 const float *__restrict__ zbar, float *__restrict__ gZ,
-                                                int seg, int xgrp)
+                                                int seg, int xgrp, unsigned long long *__restrict__ fix,
+                                                const double *__restrict__ fscale)
 {
     constexpr int LPR = 64 / RB;                 // lanes per ray
-    constexpr int G = LPR * kScatterSpl;         // depths per group
     constexpr int CAP = ScatterBox<RB>::cap;
     // s_box is all zeros between groups: cleared once here, and every flush
     // clears the entries it reads
@@ -1373,21 +1373,36 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
     }
     const float *zrow = zbar + fr.out_offset + (long long)(ray_ok ? j : 0) * S;
     const int sxy = v.nx * v.ny;
+    // depths per lane (4, 2 or 1) from the step length in voxels, so that a
+    // group spans about 11 voxels along the rays and its box fits LDS also
+    // for coarse steps (one sample per voxel and more); the wavefront's
+    // first ray decides (the rays of a fan share their step length)
+    int spl;
+    {
+        const double s2 = ray.du[0] * ray.du[0] + ray.du[1] * ray.du[1] + ray.du[2] * ray.du[2];
+        spl = (s2 <= 0.35 * 0.35) ? 4 : ((s2 <= 0.7 * 0.7) ? 2 : 1);
+        spl = __builtin_amdgcn_readfirstlane(spl);
+    }
+    const int G = LPR * spl;                     // depths per group (divides LPR kScatterSpl)
+    // deterministic mode: 64-bit fixed-point sums (integer adds, in any
+    // order the same) with the step's scale instead of FP32 atomics
+    const double fsc = fix ? fscale[0] : 0.0;
     for (int t = lane; t < CAP; t += 64) s_box[t] = 0.0;
-    // dL/dZ of the next group is loaded one group ahead
+    // dL/dZ of the next group is loaded one group ahead; the lane's depths
+    // past spl stay zero (inactive)
     float zn[kScatterSpl];
 #pragma unroll
     for (int q = 0; q < kScatterSpl; ++q) {
-        const int k = k_begin + ch * kScatterSpl + q;
-        zn[q] = (ray_ok && k < k_end) ? zrow[k] : 0.0f;
+        const int k = k_begin + ch * spl + q;
+        zn[q] = (ray_ok && q < spl && k < k_end) ? zrow[k] : 0.0f;
     }
     for (int k0 = k_begin; k0 < k_end; k0 += G) {
         float zb[kScatterSpl];
 #pragma unroll
         for (int q = 0; q < kScatterSpl; ++q) {
             zb[q] = zn[q];
-            const int k = k0 + G + ch * kScatterSpl + q;
-            zn[q] = (ray_ok && k < k_end) ? zrow[k] : 0.0f;
+            const int k = k0 + G + ch * spl + q;
+            zn[q] = (ray_ok && q < spl && k < k_end) ? zrow[k] : 0.0f;
         }
         Stencil st[kScatterSpl];
         int qf = -1, ql = -1;
@@ -1395,7 +1410,7 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
         for (int q = 0; q < kScatterSpl; ++q) {
             st[q] = Stencil{0, 0, 0, 0, 0.0, 0.0, 0.0};
             if (zb[q] != 0.0f) {
-                st[q] = stencil_at(v, ray, k0 + ch * kScatterSpl + q);
+                st[q] = stencil_at(v, ray, k0 + ch * spl + q);
                 if (qf < 0) qf = q;
                 ql = q;
             }
@@ -1445,10 +1460,17 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
                                      zb[q] * wx * wy * gz, zb[q] * gx * gy * wz, zb[q] * wx * gy * wz,
                                      zb[q] * gx * wy * wz, zb[q] * wx * wy * wz};
                 const int off[8] = {0, 1, v.nx, v.nx + 1, sxy, sxy + 1, sxy + v.nx, sxy + v.nx + 1};
-                float *dst = gZ + st[q].idx;
+                if (fix) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (w8[c] != 0.0f) atomicAdd(dst + off[c], w8[c]);
+                    for (int c = 0; c < 8; ++c)
+                        if (w8[c] != 0.0f)
+                            atomicAdd(fix + st[q].idx + off[c], (unsigned long long)__double2ll_rn((double)w8[c] * fsc));
+                } else {
+                    float *dst = gZ + st[q].idx;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (w8[c] != 0.0f) atomicAdd(dst + off[c], w8[c]);
+                }
             }
             continue;
         }
@@ -1523,8 +1545,12 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
                 for (int u = 0; u < 4; ++u) {
                     if (val[u] != 0.0) {
                         s_box[at[u]] = 0.0;
-                        const float xv = (float)val[u];
-                        if (xv != 0.0f) atomicAdd(gZ + gi[u], xv);
+                        if (fix) {
+                            atomicAdd(fix + gi[u], (unsigned long long)__double2ll_rn(val[u] * fsc));
+                        } else {
+                            const float xv = (float)val[u];
+                            if (xv != 0.0f) atomicAdd(gZ + gi[u], xv);
+                        }
                     }
                 }
             }
@@ -2021,6 +2047,55 @@ __global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part,
     if (grad && pi < n_poses) pose_finalize_one(acc, poses, pi, grad);
 }
 
+// deterministic dL/dZ: the sum of |dL/dZ| over every sample of the step
+// bounds every voxel's sum (the trilinear weights of a sample are at most 1
+// and add up to 1), and sets the fixed-point scale 2^e with that bound times
+// 2^e below 2^61, so no 64-bit sum can overflow however the atomics are
+// ordered.  Each wavefront sums one ray's row (the rows of the fans only:
+// gaps between pose images are never read), in a fixed order
+__global__ __launch_bounds__(256) void k_abs_rows(FanTable tab, const float *__restrict__ zbar,
+                                                  double *__restrict__ part)
+{
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= tab.total_rays) return;            // whole wavefront
+    const FanRec fr = tab.f[find_fan(tab, g)];
+    const int S = fr.n_samples;
+    const float *row = zbar + fr.out_offset + (long long)(g - fr.ray_begin) * S;
+    double acc = 0.0;
+    for (int k = lane; k < S; k += 64) acc += fabs((double)row[k]);
+    acc = wave_sum(acc);
+    if (lane == 0) part[g] = acc;
+}
+
+// fscale[2] = the sum of the n per-ray sums (one block, fixed order), and
+// fscale[0..1] = 2^e, 2^-e
+__global__ __launch_bounds__(256) void k_fix_scale(const double *__restrict__ part, long long n,
+                                                   double *__restrict__ fscale)
+{
+    sum_block(part, n, fscale + 2, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double a = fscale[2];
+        const int e = (a > 0.0 && isfinite(a)) ? 60 - ilogb(a) : 0;
+        fscale[0] = ldexp(1.0, e);
+        fscale[1] = ldexp(1.0, -e);
+    }
+}
+
+// grad_Z (+)= the fixed-point sums times 2^-e, rounded once to FP32
+__global__ __launch_bounds__(256) void k_fix_to_f32(const unsigned long long *__restrict__ fix, long long n,
+                                                    const double *__restrict__ fscale, float *__restrict__ gZ,
+                                                    int overwrite)
+{
+    const double inv = fscale[1];
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const double x = (double)(long long)fix[i] * inv;
+        gZ[i] = overwrite ? (float)x : (float)((double)gZ[i] + x);
+    }
+}
+
 // two buffers cleared in one launch (grid-stride over both)
 __global__ void k_zero_pair(float *__restrict__ a, long long na, double *__restrict__ b, long long nb)
 {
@@ -2343,10 +2418,11 @@ hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double
 }
 
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
-                          const RayRec *rays, const float *zbar, float *gZ, hipStream_t st)
+                          const RayRec *rays, const float *zbar, float *gZ, hipStream_t st,
+                          unsigned long long *fix, const double *fscale)
 {
-    if (t.total_rays <= 0 || !gZ) return hipSuccess;
-    if (!zbar || !rays) return hipErrorInvalidValue;
+    if (t.total_rays <= 0 || (!gZ && !fix)) return hipSuccess;
+    if (!zbar || !rays || (fix && !fscale)) return hipErrorInvalidValue;
     // 0: automatic.  Eight rays per wavefront, unless that leaves fewer than
     // two wavefronts per SIMD; then two (more wavefronts, each walking a
     // quarter as many groups)
@@ -2367,13 +2443,16 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
     const dim3 grid(blocks, (smax + seg - 1) / seg);
     switch (scatter_rays) {
     case 2:
-        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group);
+        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group,
+                           fix, fscale);
         break;
     case 4:
-        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group);
+        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group,
+                           fix, fscale);
         break;
     case 8:
-        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group);
+        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group,
+                           fix, fscale);
         break;
     default:
         return hipErrorInvalidValue;
@@ -2542,6 +2621,28 @@ hipError_t launch_finish(const double *part, int64_t n_part, double *loss, const
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finish, dim3(grid), dim3(256), 0, st, part, (long long)n_part, loss, acc, poses, n_poses,
                        grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_abs_rows(const FanTable &t, const float *zbar, double *part, hipStream_t st)
+{
+    if (t.total_rays <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_abs_rows, dim3((t.total_rays + 3) / 4), dim3(256), 0, st, t, zbar, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_fix_scale(const double *part, int64_t n, double *fscale, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fix_scale, dim3(1), dim3(256), 0, st, part, (long long)n, fscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_fix_to_f32(const unsigned long long *fix, int64_t n, const double *fscale, float *gZ,
+                             bool overwrite, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fix_to_f32, dim3(grid_for((n + 3) / 4, 256)), dim3(256), 0, st, fix, (long long)n, fscale,
+                       gZ, overwrite ? 1 : 0);
     return hipGetLastError();
 }
 

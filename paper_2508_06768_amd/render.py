@@ -356,11 +356,12 @@ class FusedStep:
     replayed from a captured HIP graph (``dus_plan``)."""
 
     def __init__(self, geom: Geometry, pose_only: bool = False, zero_grad_z: bool = True,
-                 graph: bool = True, schedule: dict | None = None):
+                 graph: bool = True, schedule: dict | None = None, deterministic: bool = False):
         L = _lib.lib()
         self.geom = geom
         flags = (_lib.PLAN_POSE_ONLY if pose_only else 0) | (_lib.PLAN_ZERO_GRAD_Z if zero_grad_z else 0)
         flags |= 0 if graph else _lib.PLAN_NO_GRAPH
+        flags |= _lib.PLAN_DETERMINISTIC if deterministic else 0
         h = ctypes.c_void_p()
         check(L.dus_plan_create(ctypes.byref(h), ctypes.byref(geom.vol_c), geom.fans_c, geom.n_poses,
                                 ctypes.byref(geom.phys_c), flags), "dus_plan_create")

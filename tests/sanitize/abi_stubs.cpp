@@ -144,7 +144,7 @@ hipError_t launch_pose_reduce(const FanTable &t, const double *, double *, hipSt
     return hipSuccess;
 }
 hipError_t launch_scatter(int, int, const VolArgs &, const FanTable &t, const RayRec *, const float *, float *,
-                          hipStream_t)
+                          hipStream_t, unsigned long long *, const double *)
 {
     check_table(t);
     return hipSuccess;
@@ -202,6 +202,16 @@ hipError_t launch_map_backward(const float *, int64_t, const LutArgs &, const fl
     return hipSuccess;
 }
 hipError_t launch_pixel_gain(const PhysArgs &, const FanRec &, float *, hipStream_t) { return hipSuccess; }
+hipError_t launch_abs_rows(const FanTable &t, const float *, double *, hipStream_t)
+{
+    check_table(t);
+    return hipSuccess;
+}
+hipError_t launch_fix_scale(const double *, int64_t, double *, hipStream_t) { return hipSuccess; }
+hipError_t launch_fix_to_f32(const unsigned long long *, int64_t, const double *, float *, bool, hipStream_t)
+{
+    return hipSuccess;
+}
 hipError_t static_scratch(void **ptr)
 {
     *ptr = reinterpret_cast<void *>((uintptr_t)0x7000000);     // 256-byte aligned, never dereferenced

@@ -47,12 +47,15 @@ def ragged_case(refl=0, atten=0, effects=False, seed=7) -> synth.Case:
     return synth.Case("ragged48", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans, ph)
 
 
-def coarse_case(seed=5) -> synth.Case:
-    """Coarse depth steps (1.2 voxel per sample): the 64-sample groups do not
-    fit the adjoint's LDS box and take the per-sample atomic path."""
+def coarse_case(seed=5, ds=3.0) -> synth.Case:
+    """Coarse depth steps.  The scatter takes 4, 2 or 1 depths per lane as
+    the step grows (0.35 and 0.7 voxel the thresholds); at 3 voxels per
+    sample even its groups of 8 depths do not fit the LDS box and take the
+    per-sample atomic path; at 0.5 and 1 voxel (the paper's one sample per
+    voxel) the box takes groups of 16 and 8 depths."""
     Z = synth.brain_volume(seed, 40, 1.0, semi_range=(3.0, 9.0))
     poses = np.array([[19.5, 18.0, 0.0, 0.3, -0.2, 0.1]], dtype=np.float32)
-    fans = [synth.FanSpec(9, 100, 0.6, 1.2, 0.0, 0)]
+    fans = [synth.FanSpec(9, max(int(100 * 1.2 / ds), 20), 0.6, ds, 0.0, 0)]
     ph = synth.PhysicsSpec(seed=seed, speckle_on=True)
     return synth.Case("coarse40", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans, ph)
 
@@ -151,10 +154,11 @@ def test_homogeneous_volume_is_exactly_silent():
     assert np.all(img == 0.0)
 
 
-@pytest.mark.parametrize("refl,effects", [(0, False), (1, True), (0, True), ("coarse", None)])
+@pytest.mark.parametrize("refl,effects", [(0, False), (1, True), (0, True), ("coarse", 3.0), ("coarse", 1.0),
+                                          ("coarse", 0.5)])
 def test_backward_parity_ragged(refl, effects):
     from paper_2508_06768_amd.render import render_backward
-    case = coarse_case() if refl == "coarse" else ragged_case(refl, 0, effects, seed=11)
+    case = coarse_case(ds=effects) if refl == "coarse" else ragged_case(refl, 0, effects, seed=11)
     geom, Z, poses = _gpu(case)
     rng = np.random.default_rng(3)
     w = rng.standard_normal(geom.total).astype(np.float32)

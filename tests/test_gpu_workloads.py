@@ -209,6 +209,82 @@ def test_bench_workload_full_size(schedule):
     step.close()
 
 
+def _det_run(case, target, graph=True, zero=True, init=None, replays=3):
+    from paper_2508_06768_amd.render import FusedStep
+    geom, Z, P = _gpu(case)
+    T = torch.from_numpy(target.astype(np.float32)).to(DEV)
+    step = FusedStep(geom, zero_grad_z=zero, graph=graph, deterministic=True)
+    out = []
+    for _ in range(replays):
+        gZ = torch.full_like(Z, init if init is not None else 0.0)
+        gp = torch.empty((geom.n_poses, 6), device=DEV)
+        loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+        step.step(Z, P, T, loss=loss, grad_Z=gZ, grad_pose=gp)
+        torch.cuda.synchronize()
+        out.append((gZ.cpu().numpy(), gp.cpu().numpy(), loss.item()))
+        _ = (Z * 2).sum().item()            # unrelated eager work between replays
+    step.close()
+    return out
+
+
+@pytest.mark.parametrize("which", ["ragged", "bench8"])
+def test_deterministic_plan(which):
+    """DUS_PLAN_DETERMINISTIC sums dL/dZ as 64-bit fixed point: graph
+    replays and the eager step give bit-identical dL/dZ (fresh buffers each
+    time), which matches the oracle to the 1e-5 bars; without the clear flag
+    the result is added to what grad_Z held."""
+    from tests.test_gpu_parity import ragged_case
+    if which == "ragged":
+        case = ragged_case(0, 0, True, seed=45)
+        target = H.oracle_render(case, poses=case.poses + np.float32([[0.4, -0.2, 0.3, 0.02, 0.0, -0.01]]))
+    else:
+        case = synth.case_batched_c2(B=8)
+        target = H.oracle_render(case, poses=case.extra["target_poses"])
+    print("case", which, "ray-samples", case.ray_samples, flush=True)
+    runs = _det_run(case, target) + _det_run(case, target, graph=False, replays=1)
+    for gZ, gp, loss in runs[1:]:
+        np.testing.assert_array_equal(gZ, runs[0][0])
+        np.testing.assert_array_equal(gp, runs[0][1])
+    img, ref_loss, rV, rp = _plan_reference(case, target)
+    assert runs[0][2] == pytest.approx(ref_loss, rel=1e-5)
+    check_grad_volume(runs[0][0], rV, f"deterministic {which}")
+    check_grad_pose(runs[0][1], rp, f"deterministic {which}")
+    acc = _det_run(case, target, zero=False, init=123.0, replays=1)[0][0]
+    check_grad_volume(acc.astype(np.float64) - 123.0, rV.astype(np.float64), f"deterministic {which} +=")
+
+
+def test_deterministic_plan_gapped_images():
+    """Pose images with gaps between them (never written): the fixed-point
+    bound sums the fans' own rows, so NaN bytes left in the workspace's gaps
+    change nothing."""
+    from paper_2508_06768_amd.render import FusedStep
+    from tests.test_gpu_parity import ragged_case
+    case = ragged_case(0, 0, False, seed=46)
+    target = H.oracle_render(case, poses=case.poses + np.float32([[0.3, 0.2, -0.2, 0.0, 0.02, 0.01]]))
+    geom, Z, P = _gpu(case)
+    gap = 1001
+    packed = geom.offsets.copy()
+    for i in range(geom.n_poses):
+        geom.fans_c[i].out_offset = int(packed[i] + gap * (i + 1))
+    geom.total = int(packed[-1] + gap * (geom.n_poses + 1))
+    Tg = np.zeros(geom.total, np.float32)
+    for i in range(geom.n_poses):
+        o = int(geom.fans_c[i].out_offset)
+        Tg[o:o + packed[i + 1] - packed[i]] = target[packed[i]:packed[i + 1]]
+    step = FusedStep(geom, zero_grad_z=True, deterministic=True)
+    step.workspace(Z.device).fill_(0xFF)        # NaN in every FP32 word of the workspace
+    gZ = torch.empty_like(Z)
+    gp = torch.empty((geom.n_poses, 6), device=DEV)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    step.step(Z, P, torch.from_numpy(Tg).to(DEV), loss=loss, grad_Z=gZ, grad_pose=gp)
+    torch.cuda.synchronize()
+    step.close()
+    img, ref_loss, rV, rp = _plan_reference(case, target)
+    assert loss.item() == pytest.approx(ref_loss, rel=1e-5)
+    check_grad_volume(gZ.cpu().numpy(), rV, "deterministic gapped")
+    check_grad_pose(gp.cpu().numpy(), rp, "deterministic gapped")
+
+
 def test_schedules_agree():
     from paper_2508_06768_amd.render import get_schedule, render, render_backward, set_schedule
     from tests.test_gpu_parity import ragged_case
