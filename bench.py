@@ -12,7 +12,8 @@ volume, cleared every step) and dL/dpose -- one captured HIP graph per step
 Printed: one JSON line with ray-samples/s of that step, the same for the
 plain per-pose form and the forward-only form, the uneven 64-pose batch
 (128-512 rays x 256-2048 samples per pose) in its batched and plain forms,
-the roofline of the dominant kernel (HIP events on the launch stream) and the
+a batch of very uneven ray lengths (63 fans of 256 x 256 samples and one of
+64 x 16384) beside the same ray-samples spread evenly, the roofline of the dominant kernel (HIP events on the launch stream) and the
 FP64 CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--poses B] [--gpus 1]
@@ -208,6 +209,34 @@ def uneven_batch(Z, dev, reps: int, plain: bool, ev):
     return res
 
 
+def skewed_batch(Z, dev, reps: int, ev):
+    """A batch whose ray lengths are very uneven (63 fans of 256 x 256
+    samples and one of 64 x 16384, speckle + blur) and the same ray-samples
+    spread over 64 fans of 256 x 316: the fused step (graph), with the long
+    rays walked by several wavefronts each (the default) and by one."""
+    import torch
+
+    from paper_2508_06768_amd import synth
+    from paper_2508_06768_amd.render import FusedStep, Geometry, render
+
+    res = {}
+    for name, case, span in (("skewed", synth.case_skewed(), 0), ("skewed_one_wave_per_ray", synth.case_skewed(), -1),
+                             ("even", synth.case_skewed(even=True), 0)):
+        geom = Geometry(case.Z.shape, case.spacing, case.origin, case.fans, case.phys)
+        poses = torch.from_numpy(case.poses).to(dev)
+        target = render(Z, torch.from_numpy(case.extra["target_poses"]).to(dev), geom).clone()
+        step = FusedStep(geom, zero_grad_z=True, schedule={"span_samples": span})
+        gZ = torch.zeros_like(Z)
+        gp = torch.empty((geom.n_poses, 6), device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        fused = lambda: step.step(Z, poses, target, loss=loss, grad_Z=gZ, grad_pose=gp)  # noqa: E731
+        fused()
+        ms = timed(fused, reps, ev)
+        res[name] = {"ms": ms, "value": geom.total / (ms * 1e-3), "ray_samples_per_step": geom.total}
+        step.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +380,9 @@ def main():
     log("bench: uneven 64-pose batch")
     uneven = uneven_batch(Z, dev, max(5, args.steps // 2), not args.no_plain, ev)
     log(f"bench: uneven batch {json.dumps(uneven)}")
+    log("bench: skewed batch")
+    skewed = skewed_batch(Z, dev, max(5, args.steps // 2), ev)
+    log(f"bench: skewed batch {json.dumps(skewed)}")
 
     if args.calib_copy:
         src = torch.empty(CALIB_BYTES // 4, device=dev).fill_(1.0)
@@ -426,6 +458,7 @@ def main():
             "alu": alu,
         },
         "uneven_batch": uneven,
+        "skewed_batch": skewed,
         "schedule": step.get_schedule(),
         "autotune_trials": None if tune is None else tune.get("trials"),
         "cpu_baseline": cpu,

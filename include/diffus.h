@@ -320,8 +320,13 @@ typedef struct {
     int32_t bwd_chunk;        /* same for the adjoint: 4 or 8 */
     int32_t xcd_group;        /* consecutive rays kept on one XCD: 1..64 */
     int32_t scatter_rays;     /* neighbouring rays per wavefront (one LDS box) in the dL/dZ scatter:
-                                 2, 4 or 8; 0 (the default) picks 8, or 2 for launches of fewer
-                                 than 16384 rays */
+                                 2, 4 or 8; 0 (the default) picks 8, or 2 when even the shortest
+                                 depth segments would give fewer than 2048 wavefronts */
+    int32_t span_samples;     /* rays of at least this many samples are walked by several
+                                 wavefronts each, which take consecutive tiles of the ray together
+                                 (forward; the plan's adjoint): 1..DUS_MAX_SAMPLES, 0 (the default)
+                                 for 4096, -1 for never.  Results do not depend on it, except for
+                                 the rounding of the pose gradient and of the fused loss */
 } dus_schedule;
 
 /* Process-wide schedule used by dus_render_bmode / dus_render_bmode_backward

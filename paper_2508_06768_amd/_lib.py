@@ -44,7 +44,8 @@ class DusPhysics(ctypes.Structure):
 
 
 class DusSchedule(ctypes.Structure):
-    _fields_ = [("fwd_chunk", c_i32), ("bwd_chunk", c_i32), ("xcd_group", c_i32), ("scatter_rays", c_i32)]
+    _fields_ = [("fwd_chunk", c_i32), ("bwd_chunk", c_i32), ("xcd_group", c_i32), ("scatter_rays", c_i32),
+                ("span_samples", c_i32)]
 
 
 class DusGrid2d(ctypes.Structure):

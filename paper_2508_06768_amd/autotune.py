@@ -3,7 +3,9 @@
 The kernels take a ray-to-wavefront schedule (``dus_schedule``): interfaces
 per lane per tile in the forward (4, 8, 16) and the adjoint (4, 8), the
 number of neighbouring rays that share one LDS box in the dL/dZ scatter (2,
-4, 8), and the number of consecutive rays kept on one XCD (1..64).
+4, 8), the number of consecutive rays kept on one XCD (1..64), and the ray
+length from which several wavefronts share a ray (``span_samples``: never,
+or 1024..8192 samples, tried only up to the plan's longest ray).
 ``autotune`` times the candidates on the caller's actual plan and inputs
 with HIP events (coordinate descent in that order, each candidate over
 ``reps`` steps), installs the fastest on the plan and remembers it in a JSON
@@ -22,6 +24,7 @@ FWD_CHUNKS = (4, 8, 16)
 BWD_CHUNKS = (4, 8)
 XCD_GROUPS = (1, 4, 8, 16, 32, 64)
 SCATTER_RAYS = (2, 4, 8)
+SPAN_SAMPLES = (-1, 1024, 2048, 4096, 8192)
 
 
 def _cache_path() -> str:
@@ -97,8 +100,10 @@ def autotune(step, run, reps: int = 10, use_cache: bool = True, verbose: bool = 
         return ms
 
     best_ms = trial(best)
+    longest = max((int(f.n_samples) for f in step.geom.fans), default=0)
+    spans = tuple(v for v in SPAN_SAMPLES if v <= longest)
     for field, values in (("fwd_chunk", FWD_CHUNKS), ("bwd_chunk", BWD_CHUNKS), ("scatter_rays", SCATTER_RAYS),
-                          ("xcd_group", XCD_GROUPS)):
+                          ("xcd_group", XCD_GROUPS), ("span_samples", spans)):
         for val in values:
             if val == best[field]:
                 continue

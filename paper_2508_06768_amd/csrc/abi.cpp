@@ -344,6 +344,7 @@ struct Sched {
     int bwd_chunk = kDefaultBwdChunk;
     int xcd_group = kDefaultXcdGroup;
     int scatter_rays = kDefaultScatterRays;
+    int span_samples = dus::kSpanSamples;
 };
 
 Sched g_sched;     // schedule of the direct (non-plan) calls
@@ -359,6 +360,9 @@ int make_sched(const dus_schedule *sc, Sched &n)
     if (n.fwd_chunk != 4 && n.fwd_chunk != 8 && n.fwd_chunk != 16) return fail(DUS_EINVAL, "fwd_chunk must be 4, 8 or 16");
     if (n.bwd_chunk != 4 && n.bwd_chunk != 8) return fail(DUS_EINVAL, "bwd_chunk must be 4 or 8");
     if (n.xcd_group < 1 || n.xcd_group > 64) return fail(DUS_EINVAL, "xcd_group must be in [1, 64]");
+    n.span_samples = sc->span_samples ? sc->span_samples : dus::kSpanSamples;
+    if (n.span_samples != -1 && (n.span_samples < 1 || n.span_samples > DUS_MAX_SAMPLES))
+        return fail(DUS_EINVAL, "span_samples must be 0 (default), -1 (never) or in [1, DUS_MAX_SAMPLES]");
     return DUS_OK;
 }
 
@@ -372,7 +376,7 @@ int enqueue_forward(const Sched &sc, const dus::VolArgs &va, const dus::PhysArgs
     for (const auto &t : tabs) {
         if (t.total_rays <= 0) continue;
         DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, out, min_pivot, 0, carry,
-                                    carry_exp, cstate, gain, st, first ? zero : dus::ZeroArgs{}),
+                                    carry_exp, cstate, gain, st, first ? zero : dus::ZeroArgs{}, sc.span_samples),
                 "forward kernel launch");
         first = false;
     }
@@ -767,6 +771,7 @@ int dus_get_schedule(dus_schedule *sc)
     sc->bwd_chunk = g_sched.bwd_chunk;
     sc->xcd_group = g_sched.xcd_group;
     sc->scatter_rays = g_sched.scatter_rays;
+    sc->span_samples = g_sched.span_samples;
     return DUS_OK;
 }
 
@@ -777,6 +782,7 @@ int dus_plan_get_schedule(const dus_plan *p, dus_schedule *sc)
     sc->bwd_chunk = p->sched.bwd_chunk;
     sc->xcd_group = p->sched.xcd_group;
     sc->scatter_rays = p->sched.scatter_rays;
+    sc->span_samples = p->sched.span_samples;
     return DUS_OK;
 }
 
@@ -861,7 +867,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
                                         grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0,
                                         (!blur && loss) ? part + n_part : nullptr,
                                         fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? cst : nullptr,
-                                        fwd ? gain : nullptr, st),
+                                        fwd ? gain : nullptr, st, sc.span_samples),
                     "adjoint kernel");
             if (!blur) n_part += t.total_rays;
             r0 += t.total_rays;

@@ -8,6 +8,12 @@ namespace dus {
 
 // Fans per launch: the fan table travels in the kernel arguments.
 constexpr int kMaxFans = 64;
+// rays of at least span_samples samples (kSpanSamples by default; <= 0:
+// none) are walked by kSpanWaves wavefronts each, which take consecutive
+// tiles of the ray together (forward and plan adjoint); shorter rays by one
+// wavefront
+constexpr int kSpanSamples = 4096;
+constexpr int kSpanWaves = 8;
 
 struct FanRec {
     int32_t n_rays, n_samples;
@@ -103,7 +109,8 @@ struct ZeroArgs {
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out,
                           float *min_pivot, int pivot_base, double *carry, int32_t *carry_exp,
-                          double *cstate, float *gain, hipStream_t st, const ZeroArgs &zero = ZeroArgs{});
+                          double *cstate, float *gain, hipStream_t st, const ZeroArgs &zero = ZeroArgs{},
+                          int span_samples = kSpanSamples);
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
 // the fused form (target given) loss receives one partial per ray.  With
 // pose_acc (a flag here), pose_part receives kRayPart doubles per ray of the
@@ -122,7 +129,7 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
                           const FanTable &t, const float *poses, RayRec *rays, const float *gsrc,
                           const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
-                          const float *gain, hipStream_t st);
+                          const float *gain, hipStream_t st, int span_samples = kSpanSamples);
 // pose_acc[pose] += the sum of the table's per-ray partials, one wavefront
 // per fan (fixed order)
 hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double *pose_acc, hipStream_t st);

@@ -626,31 +626,47 @@ __device__ __forceinline__ int renorm_exp(double c0, double c1)
 
 // --------------------------------------------------------------------------
 // forward kernel
+//
+// W = 1: one wavefront per ray walks its tiles in order.  W > 1 (rays of
+// many tiles): W wavefronts share a ray and take W consecutive tiles at a
+// time.  A tile's gather, chunk products and lane scan need nothing from the
+// tiles before it; only the state carried into its walk does, and that is
+// the state at the round's start pushed through the scan totals of the
+// tiles before it (one 1x2 by 2x2 product and a power-of-two renormalisation
+// per tile, in the order and with the operations of W = 1, so the results
+// are the same bit for bit).  The sample before the tile comes from its own
+// trilinear lookup instead of the previous tile's gather.
 // --------------------------------------------------------------------------
-template <int C, bool SPK>
-__global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable tab,
-                                                const float *__restrict__ poses,
-                                                float *__restrict__ out, float *__restrict__ minpiv,
-                                                int pivot_base, double *__restrict__ carry,
-                                                int32_t *__restrict__ carry_exp,
-                                                double *__restrict__ cstate,
-                                                float *__restrict__ gain_out, int xgrp, ZeroArgs zero)
+template <int C, bool SPK, int W>
+__global__ __launch_bounds__(64 * W) void k_forward(VolArgs v, PhysArgs p, FanTable tab,
+                                                    const float *__restrict__ poses,
+                                                    float *__restrict__ out, float *__restrict__ minpiv,
+                                                    int pivot_base, double *__restrict__ carry,
+                                                    int32_t *__restrict__ carry_exp,
+                                                    double *__restrict__ cstate,
+                                                    float *__restrict__ gain_out, int g0, int xgrp, ZeroArgs zero)
 {
     constexpr int T = 64 * C;
     static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
     static_assert(C % kStateStride == 0, "chunks hold whole state strides");
     constexpr int NB = T / kCarryBlock;     // carry blocks per tile
     constexpr int LB = kCarryBlock / C;     // lanes per carry block
-    __shared__ double s_rho[T + T / 16];
-    __shared__ double s_zc[NB];
-    __shared__ float s_xir[SPK ? T / 4 + 8 : 1];
+    __shared__ double s_rho_w[W][T + T / 16];
+    __shared__ double s_zc_w[W][NB];
+    __shared__ float s_xir_w[W][SPK ? T / 4 + 8 : 1];
+    __shared__ double s_tot[W > 1 ? W : 1][5];     // scan totals of a round's tiles
+    __shared__ double s_piv[W > 1 ? W : 1];
 
-    const int lane = threadIdx.x;
+    const int lane = (W == 1) ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    const int wv = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    double *s_rho = s_rho_w[wv];
+    double *s_zc = s_zc_w[wv];
+    float *s_xir = s_xir_w[wv];
     if (zero.na > 0 || zero.nb > 0) {
         // the step's clears, spread over the forward's wavefronts: the stores
         // drain while the wavefront renders its ray
-        const long long stride = (long long)gridDim.x * 64;
-        const long long i0 = (long long)blockIdx.x * 64 + lane;
+        const long long stride = (long long)gridDim.x * 64 * W;
+        const long long i0 = (long long)blockIdx.x * 64 * W + threadIdx.x;
         if ((reinterpret_cast<uintptr_t>(zero.a) & 15) == 0) {
             float4 *a4 = reinterpret_cast<float4 *>(zero.a);
             const long long n4 = zero.na / 4;
@@ -661,7 +677,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
         }
         for (long long i = i0; i < zero.nb; i += stride) zero.b[i] = 0.0;
     }
-    const int g = remap_block(blockIdx.x, gridDim.x, xgrp);
+    const int g = g0 + remap_block(blockIdx.x, gridDim.x, xgrp);
     const int fi = find_fan(tab, g);
     const FanRec fr = tab.f[fi];
     const int j = g - fr.ray_begin;
@@ -675,6 +691,7 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     const GainK gk = gain_consts(p, fr.n_samples);
     const long long obase = fr.out_offset + (long long)j * S;
 
+    // state carried into the round (W > 1) or the tile (W = 1)
     double c0 = 0.0, c1 = 1.0, cD = d_start(a2), zprev = 0.0;
     double piv = 1e300;
     const bool want_piv = (minpiv != nullptr);
@@ -682,141 +699,184 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     const long long crec = (long long)fr.carry_begin + (long long)j * nblk;
     int first_rel = 0;      // exponent of this tile's carry relative to the previous record
 
-    for (int t0 = 0; t0 < S; t0 += T) {
+    for (int r0 = 0; r0 < S; r0 += W * T) {
+        const int t0 = r0 + wv * T;
+        const bool act = (W == 1) || (t0 < S);      // uniform over the wavefront
+        if (W > 1 && act && t0 > 0) {
+            const Stencil st = stencil_at<false>(v, ray, t0 - 1);
+            zprev = trilinear(v.Z, v.nx, v.nx * v.ny, st, nullptr);
+        }
         const double zstart = zprev;
-        gather_tile<C, false>(v, ray, t0, S, absm, lane, zprev, s_rho, nullptr, nullptr,
-                              carry ? s_zc : nullptr);
-        if (SPK) speckle_radial<T>(p, t0, j, fr.speckle_id, lane, s_xir);
+        if (act) {
+            gather_tile<C, false>(v, ray, t0, S, absm, lane, zprev, s_rho, nullptr, nullptr,
+                                  carry ? s_zc : nullptr);
+            if (SPK) speckle_radial<T>(p, t0, j, fr.speckle_id, lane, s_xir);
+        }
         __syncthreads();
 
         const int base = lane * C;
         Mat Q, X, Tot;
         double qd, xd, td;
-        chunk_product<C, false>(s_rho, base, t0, S, a2, sgn, Q, qd);
-        scan_exclusive(lane, Q, qd, X, xd, Tot, td);
-        double v0 = fma(c0, X.a, c1 * X.c);
-        double v1 = fma(c0, X.b, c1 * X.d);
-        double D = cD * xd;
-        if (carry) {
-            // state at the start of carry block m = lane / LB (lanes on a
-            // block boundary), in the tile's frame: inside a tile the
-            // records share one scale, so only a tile's first record carries
-            // an exponent (relative to the previous record)
-            const int m = lane / LB;
-            const int kb = t0 + m * kCarryBlock;
-            if ((lane % LB) == 0 && kb < S) {
-                const long long r = crec + kb / kCarryBlock;
-                double *q = carry + 4 * r;
-                q[0] = v0;
-                q[1] = v1;
-                // the ray's first record in the adjoint's convention (identity
-                // map before sample 0): D = 1
-                q[2] = (kb == 0) ? 1.0 : D;
-                q[3] = (m == 0) ? zstart : s_zc[m - 1];
-                carry_exp[r] = (m == 0) ? first_rel : 0;
+        double tc0 = c0, tc1 = c1, tcD = cD;        // the state carried into this tile
+        int trel = first_rel;
+        if (act) {
+            chunk_product<C, false>(s_rho, base, t0, S, a2, sgn, Q, qd);
+            scan_exclusive(lane, Q, qd, X, xd, Tot, td);
+        }
+        if (W > 1) {
+            if (act && lane == 0) {
+                s_tot[wv][0] = Tot.a;
+                s_tot[wv][1] = Tot.b;
+                s_tot[wv][2] = Tot.c;
+                s_tot[wv][3] = Tot.d;
+                s_tot[wv][4] = td;
+            }
+            __syncthreads();
+            // the round's carry through the tiles before this one; then on
+            // through the rest of the round for the next round's carry
+            for (int u = 0; u < W; ++u) {
+                if (u == wv) {
+                    tc0 = c0;
+                    tc1 = c1;
+                    tcD = cD;
+                    trel = first_rel;
+                }
+                if (r0 + u * T >= S) break;
+                const double n0 = fma(c0, s_tot[u][0], c1 * s_tot[u][2]);
+                const double n1 = fma(c0, s_tot[u][1], c1 * s_tot[u][3]);
+                const double nD = cD * s_tot[u][4];
+                const int ex = renorm_exp(n0, n1);
+                c0 = ldexp(n0, -ex);
+                c1 = ldexp(n1, -ex);
+                cD = ldexp(nD, -2 * ex);
+                first_rel = ex;
             }
         }
-        // chunk states for the adjoint: the lane's C samples lie in one
-        // carry block (the ray's first state is taken in the adjoint's
-        // convention by the adjoint itself)
-        double *qs = nullptr;
-        if (cstate && (t0 + base) / kCarryBlock < nblk)
-            qs = cstate + (crec + (t0 + base) / kCarryBlock) * kStateDoubles + ((t0 + base) % kCarryBlock) / kStateStride;
-        float pix[C];
-#pragma unroll
-        for (int i = 0; i < C; ++i) {
-            // branch-free: outside [1, S) rho = 0, so the pixel is 0 and v1
-            // unchanged (make_map)
-            const int k = t0 + base + i;
-            // the chunk states and the gains below are read once, by the
-            // adjoint after the blur: non-temporal stores keep them from
-            // displacing the volume and the images in the caches
-            if ((i % kStateStride) == 0 && qs) {
-                __builtin_nontemporal_store(v0, qs + i / kStateStride);
-                __builtin_nontemporal_store(v1, qs + kStatesPerBlock + i / kStateStride);
-                __builtin_nontemporal_store(D, qs + 2 * kStatesPerBlock + i / kStateStride);
-            }
-            const double r = s_rho[pad8(base + i)];
-            const Map m = make_map(r, a2, sgn);
-            const double v1n = fma(v0, r, v1);
-            // the pixel leaves in FP32: the hardware FP64 reciprocal, without
-            // the Newton step, is accurate well beyond that
-            pix[i] = (float)(r * D * __builtin_amdgcn_rcp(v1 * v1n));
-            if (want_piv) piv = (k >= 1 && k < S) ? fmin(piv, fabs(v1n * rcp64(v1))) : piv;
-            const double v0n = fma(v0, m.m00, v1 * m.m10);
-            v0 = v0n;
-            v1 = v1n;
-            D *= m.det;
-        }
-        // carry to the next tile, renormalised by a power of two
-        {
-            const double n0 = fma(c0, Tot.a, c1 * Tot.c);
-            const double n1 = fma(c0, Tot.b, c1 * Tot.d);
-            const double nD = cD * td;
-            const int ex = renorm_exp(n0, n1);
-            c0 = ldexp(n0, -ex);
-            c1 = ldexp(n1, -ex);
-            cD = ldexp(nD, -2 * ex);
-            first_rel = ex;
-        }
-        // per-pixel gains and the stores, in the lane's chunk order (the
-        // lane's C samples start at a multiple of 4: its granular variates
-        // are C/4 whole Philox blocks)
-        float gn[C];
-#pragma unroll
-        for (int i = 0; i < C; ++i) gn[i] = 1.0f;
-        if (SPK) {
-#pragma unroll
-            for (int q = 0; q < C / 4; ++q) {
-                float x[4];
-                granular4(p, ((t0 + base) >> 2) + q, j, fr.speckle_id, x);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) gn[4 * q + u] = x[u];
-            }
-            // the lane's samples are consecutive: the radial cell index of the
-            // first is exact (cell_of), the others step it
-            int c, r;
-            cell_of(p, gk, t0 + base, c, r);
-            c -= t0 / p.cell;          // index into s_xir
-#pragma unroll
-            for (int i = 0; i < C; ++i) {
-                const int k = t0 + base + i;
-                float g = speckle_mult(p, (float)k * gk.inv_sm1, (float)r * gk.inv_cell, s_xir[c], s_xir[c + 1], gn[i]);
-                if (p.atten == 1) g *= exp2f((float)((double)k * (double)postc));
-                gn[i] = g;
-                const bool wrap = (r + 1 == p.cell);
-                c += wrap ? 1 : 0;
-                r = wrap ? 0 : r + 1;
-            }
-        } else if (p.atten == 1) {
-#pragma unroll
-            for (int i = 0; i < C; ++i)
-                gn[i] = pixel_gain<false, true>(p, gk, t0 + base + i, t0, postc, 1.0f, s_xir);
-        }
-        const bool has_gain = SPK || p.atten == 1;
-        const long long o = obase + t0 + base;
-        const bool vec = ((reinterpret_cast<uintptr_t>(out + o) & 15) == 0) &&
-                         (!gain_out || (reinterpret_cast<uintptr_t>(gain_out + o) & 15) == 0);
-        if (vec && t0 + base + C <= S) {
-#pragma unroll
-            for (int q = 0; q < C / 4; ++q) {
-                const int i = 4 * q;
-                *reinterpret_cast<float4 *>(out + o + i) =
-                    make_float4(pix[i] * gn[i], pix[i + 1] * gn[i + 1], pix[i + 2] * gn[i + 2], pix[i + 3] * gn[i + 3]);
-                if (has_gain && gain_out) {
-                    float *gq = gain_out + o + i;
-                    __builtin_nontemporal_store(gn[i], gq);
-                    __builtin_nontemporal_store(gn[i + 1], gq + 1);
-                    __builtin_nontemporal_store(gn[i + 2], gq + 2);
-                    __builtin_nontemporal_store(gn[i + 3], gq + 3);
+        if (act) {
+            double v0 = fma(tc0, X.a, tc1 * X.c);
+            double v1 = fma(tc0, X.b, tc1 * X.d);
+            double D = tcD * xd;
+            if (carry) {
+                // state at the start of carry block m = lane / LB (lanes on a
+                // block boundary), in the tile's frame: inside a tile the
+                // records share one scale, so only a tile's first record carries
+                // an exponent (relative to the previous record)
+                const int m = lane / LB;
+                const int kb = t0 + m * kCarryBlock;
+                if ((lane % LB) == 0 && kb < S) {
+                    const long long r = crec + kb / kCarryBlock;
+                    double *q = carry + 4 * r;
+                    q[0] = v0;
+                    q[1] = v1;
+                    // the ray's first record in the adjoint's convention (identity
+                    // map before sample 0): D = 1
+                    q[2] = (kb == 0) ? 1.0 : D;
+                    q[3] = (m == 0) ? zstart : s_zc[m - 1];
+                    carry_exp[r] = (m == 0) ? trel : 0;
                 }
             }
-        } else {
+            // chunk states for the adjoint: the lane's C samples lie in one
+            // carry block (the ray's first state is taken in the adjoint's
+            // convention by the adjoint itself)
+            double *qs = nullptr;
+            if (cstate && (t0 + base) / kCarryBlock < nblk)
+                qs = cstate + (crec + (t0 + base) / kCarryBlock) * kStateDoubles + ((t0 + base) % kCarryBlock) / kStateStride;
+            float pix[C];
 #pragma unroll
             for (int i = 0; i < C; ++i) {
-                if (t0 + base + i < S) {
-                    out[o + i] = pix[i] * gn[i];
-                    if (has_gain && gain_out) gain_out[o + i] = gn[i];
+                // branch-free: outside [1, S) rho = 0, so the pixel is 0 and v1
+                // unchanged (make_map)
+                const int k = t0 + base + i;
+                // the chunk states and the gains below are read once, by the
+                // adjoint after the blur: non-temporal stores keep them from
+                // displacing the volume and the images in the caches
+                if ((i % kStateStride) == 0 && qs) {
+                    __builtin_nontemporal_store(v0, qs + i / kStateStride);
+                    __builtin_nontemporal_store(v1, qs + kStatesPerBlock + i / kStateStride);
+                    __builtin_nontemporal_store(D, qs + 2 * kStatesPerBlock + i / kStateStride);
+                }
+                const double r = s_rho[pad8(base + i)];
+                const Map m = make_map(r, a2, sgn);
+                const double v1n = fma(v0, r, v1);
+                // the pixel leaves in FP32: the hardware FP64 reciprocal, without
+                // the Newton step, is accurate well beyond that
+                pix[i] = (float)(r * D * __builtin_amdgcn_rcp(v1 * v1n));
+                if (want_piv) piv = (k >= 1 && k < S) ? fmin(piv, fabs(v1n * rcp64(v1))) : piv;
+                const double v0n = fma(v0, m.m00, v1 * m.m10);
+                v0 = v0n;
+                v1 = v1n;
+                D *= m.det;
+            }
+            if (W == 1) {
+                // carry to the next tile, renormalised by a power of two
+                const double n0 = fma(c0, Tot.a, c1 * Tot.c);
+                const double n1 = fma(c0, Tot.b, c1 * Tot.d);
+                const double nD = cD * td;
+                const int ex = renorm_exp(n0, n1);
+                c0 = ldexp(n0, -ex);
+                c1 = ldexp(n1, -ex);
+                cD = ldexp(nD, -2 * ex);
+                first_rel = ex;
+            }
+            // per-pixel gains and the stores, in the lane's chunk order (the
+            // lane's C samples start at a multiple of 4: its granular variates
+            // are C/4 whole Philox blocks)
+            float gn[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i) gn[i] = 1.0f;
+            if (SPK) {
+#pragma unroll
+                for (int q = 0; q < C / 4; ++q) {
+                    float x[4];
+                    granular4(p, ((t0 + base) >> 2) + q, j, fr.speckle_id, x);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) gn[4 * q + u] = x[u];
+                }
+                // the lane's samples are consecutive: the radial cell index of the
+                // first is exact (cell_of), the others step it
+                int c, r;
+                cell_of(p, gk, t0 + base, c, r);
+                c -= t0 / p.cell;          // index into s_xir
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const int k = t0 + base + i;
+                    float g = speckle_mult(p, (float)k * gk.inv_sm1, (float)r * gk.inv_cell, s_xir[c], s_xir[c + 1], gn[i]);
+                    if (p.atten == 1) g *= exp2f((float)((double)k * (double)postc));
+                    gn[i] = g;
+                    const bool wrap = (r + 1 == p.cell);
+                    c += wrap ? 1 : 0;
+                    r = wrap ? 0 : r + 1;
+                }
+            } else if (p.atten == 1) {
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    gn[i] = pixel_gain<false, true>(p, gk, t0 + base + i, t0, postc, 1.0f, s_xir);
+            }
+            const bool has_gain = SPK || p.atten == 1;
+            const long long o = obase + t0 + base;
+            const bool vec = ((reinterpret_cast<uintptr_t>(out + o) & 15) == 0) &&
+                             (!gain_out || (reinterpret_cast<uintptr_t>(gain_out + o) & 15) == 0);
+            if (vec && t0 + base + C <= S) {
+#pragma unroll
+                for (int q = 0; q < C / 4; ++q) {
+                    const int i = 4 * q;
+                    *reinterpret_cast<float4 *>(out + o + i) =
+                        make_float4(pix[i] * gn[i], pix[i + 1] * gn[i + 1], pix[i + 2] * gn[i + 2], pix[i + 3] * gn[i + 3]);
+                    if (has_gain && gain_out) {
+                        float *gq = gain_out + o + i;
+                        __builtin_nontemporal_store(gn[i], gq);
+                        __builtin_nontemporal_store(gn[i + 1], gq + 1);
+                        __builtin_nontemporal_store(gn[i + 2], gq + 2);
+                        __builtin_nontemporal_store(gn[i + 3], gq + 3);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    if (t0 + base + i < S) {
+                        out[o + i] = pix[i] * gn[i];
+                        if (has_gain && gain_out) gain_out[o + i] = gn[i];
+                    }
                 }
             }
         }
@@ -824,7 +884,16 @@ __global__ __launch_bounds__(64) void k_forward(VolArgs v, PhysArgs p, FanTable 
     }
     if (want_piv) {
         piv = wave_min(piv);
-        if (lane == 0) minpiv[pivot_base + fr.pivot_begin + j] = (float)piv;
+        if (W == 1) {
+            if (lane == 0) minpiv[pivot_base + fr.pivot_begin + j] = (float)piv;
+        } else {
+            if (lane == 0) s_piv[wv] = piv;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int u = 1; u < W; ++u) piv = fmin(piv, s_piv[u]);
+                minpiv[pivot_base + fr.pivot_begin + j] = (float)piv;
+            }
+        }
     }
 }
 
@@ -861,8 +930,19 @@ __device__ __forceinline__ Adj adj_step(const Adj &a, double v0, double v1, doub
     return n;
 }
 
-template <int C, bool SPK, bool FUSED>
-__global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable tab,
+// W = 1: one wavefront per ray walks its tiles from the deepest up.  W > 1
+// (rays of many tiles, with the forward's carry records and chunk states):
+// W wavefronts share a ray and take W consecutive tiles at a time.  Walk 1
+// and the lanes' suffix composition need nothing from the deeper tiles; the
+// adjoint entering each tile is the round's incoming adjoint pushed through
+// the deeper tiles' affine maps (lane 1's suffix map, then lane 0's chunk
+// map, then the frame's power of two: the operations of W = 1, in its
+// order, so the results are the same bit for bit).  The sample after a
+// tile and its interface's dL/dZ factor come from the neighbouring
+// wavefront's LDS; the pose sums and the loss are added over the W
+// wavefronts in a fixed order.
+template <int C, bool SPK, bool FUSED, int W>
+__global__ __launch_bounds__(64 * W) void k_backward(VolArgs v, PhysArgs p, FanTable tab,
                                                  const float *__restrict__ poses,
                                                  RayRec *__restrict__ rays_out,
                                                  const float *__restrict__ gsrc,
@@ -873,27 +953,37 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                                                  const double *__restrict__ carry,
                                                  const int32_t *__restrict__ carry_exp,
                                                  const double *__restrict__ cstate,
-                                                 const float *__restrict__ gain_in, int xgrp)
+                                                 const float *__restrict__ gain_in, int g0, int xgrp)
 {
     constexpr int T = 64 * C;
     constexpr int kMaxTiles = (DUS_MAX_SAMPLES + T - 1) / T;
+    static_assert(W == 1 || !SPK, "several wavefronts per ray take the forward's gains");
     static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
     constexpr int NB = T / kCarryBlock;
     // walks unrolled where the registers allow three wavefronts per SIMD
     constexpr int kWalkUnroll = (C <= 4 && !SPK && !FUSED) ? C : 1;
-    __shared__ float s_g[3 * T];     // dZ/du of every sample of the tile
-    __shared__ double s_rho[T + T / 16];
-    __shared__ double s_z[T + T / 16];
-    __shared__ double s_dq[T + T / 16];   // d rho / dZ factor of every interface of the tile
-    __shared__ float s_eb[T + T / 32];
-    __shared__ float s_gain[FUSED ? T + T / 32 : 1];
+    __shared__ float s_g_w[W][3 * T];     // dZ/du of every sample of the tile
+    __shared__ double s_rho_w[W][T + T / 16];
+    __shared__ double s_z_w[W][T + T / 16];
+    __shared__ double s_dq_w[W][T + T / 16];   // d rho / dZ factor of every interface of the tile
+    __shared__ float s_eb_w[W][T + T / 32];
+    __shared__ float s_gain_w[W][FUSED ? T + T / 32 : 1];
     __shared__ float s_xig[SPK ? T : 1];
     __shared__ float s_xir[SPK ? T / 4 + 8 : 1];
     __shared__ double s_carry[kMaxTiles][4];
     __shared__ int s_cexp[kMaxTiles];
+    __shared__ double s_x[W > 1 ? W : 1][16];   // a round's tiles: lane 1's suffix map, lane 0's chunk map
+    __shared__ double s_red[W > 1 ? W : 1][7];  // per-wavefront pose sums and loss
 
-    const int lane = threadIdx.x;
-    const int g = remap_block(blockIdx.x, gridDim.x, xgrp);
+    const int lane = (W == 1) ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    const int wv = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    float *s_g = s_g_w[wv];
+    double *s_rho = s_rho_w[wv];
+    double *s_z = s_z_w[wv];
+    double *s_dq = s_dq_w[wv];
+    float *s_eb = s_eb_w[wv];
+    float *s_gain = s_gain_w[wv];
+    const int g = g0 + remap_block(blockIdx.x, gridDim.x, xgrp);
     const int fi = find_fan(tab, g);
     const FanRec fr = tab.f[fi];
     const int j = g - fr.ray_begin;
@@ -901,7 +991,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     if (S <= 0) return;
     Ray ray;
     setup_ray(v, p, fr, poses, j, ray);
-    if (rays_out && lane == 0) {
+    if (rays_out && threadIdx.x == 0) {
         // the ray's geometry for the scatter
         RayRec r;
 #pragma unroll
@@ -926,7 +1016,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     if (carry) {
         // tile starts from the forward kernel's carry records; the exponent
         // of tile t relative to tile t - 1 sums those of its carry blocks
-        for (int b = lane; b < nblk; b += 64) {
+        for (int b = threadIdx.x; b < nblk; b += 64 * W) {
             s_bexp[b] = carry_exp[rb + b];
             if (b % NB == 0) {
                 const double *q = carry + 4 * (rb + b);
@@ -939,10 +1029,10 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         __syncthreads();
         // A tile's frame is its first record renormalised by a power of two
         // (the forward's records share one scale inside a forward tile).
-        // Lane t takes tile t (ntiles <= 64): s_cexp[t] becomes the exponent
+        // Thread t takes tile t (ntiles <= 64): s_cexp[t] becomes the exponent
         // of tile t's frame relative to tile t - 1's, and s_bexp[b] that of
         // block b's record relative to its tile's frame.
-        const int t = lane;
+        const int t = threadIdx.x;
         int et = 0, cex = 0, rel[NB];
         if (t < ntiles) {
             et = renorm_exp(s_carry[t][0], s_carry[t][1]);
@@ -964,8 +1054,9 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
 #pragma unroll
             for (int u = 0; u < NB; ++u) s_bexp[t * NB + u] = rel[u];
         }
-    } else {
-        // forward sweep: state at every tile start
+    } else if (W == 1) {
+        // forward sweep: state at every tile start (several wavefronts per
+        // ray take the forward's carry records instead)
         double c0 = 0.0, c1 = 1.0, cD = 1.0, zprev = 0.0;
         for (int t = 0; t < ntiles; ++t) {
             if (lane == 0) {
@@ -995,13 +1086,17 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     }
     __syncthreads();
 
-    // reverse sweep
-    Adj lam{0.0, 0.0, 0.0};        // adjoint of the state at the current tile's end
-    double rbar_next = 0.0;        // dL/dZ factor of the interface just after this tile
-    double z_next = 0.0;           // first sample of the next tile
+    // reverse sweep (W > 1: rounds of W tiles, wavefront w taking tile rt - w)
+    Adj lam{0.0, 0.0, 0.0};        // adjoint of the state at the end of the (round's deepest) tile
+    double rbar_next = 0.0;        // dL/dZ factor of the interface just after that tile
+    double z_next = 0.0;           // first sample of the tile after it
     double loss = 0.0;
     double gsum[3] = {0.0, 0.0, 0.0}, gssum[3] = {0.0, 0.0, 0.0};
-    for (int t = ntiles - 1; t >= 0; --t) {
+    for (int rt = ntiles - 1; rt >= 0; rt -= W) {
+        // uniform over the wavefront; an idle wavefront of the last round
+        // repeats tile 0 and stores nothing
+        const bool act = (W == 1) || (rt - wv >= 0);
+        const int t = act ? rt - wv : 0;
         const int t0 = t * T;
         const double zstart = s_carry[t][3];
         double zprev = zstart;
@@ -1121,7 +1216,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                 if (FUSED) {
                     const double gn = s_gain[pad4(base + i)];
                     const double diff = e * gn - (double)s_eb[pad4(base + i)];
-                    loss += diff * diff * inv_npix;
+                    loss += act ? diff * diff * inv_npix : 0.0;
                     eb = 2.0 * diff * inv_npix * gn;
                     s_eb[pad4(base + i)] = (float)eb;
                 } else {
@@ -1168,6 +1263,53 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                 pf = Adj{n0, n1, nD};
             }
         }
+        // adjoint at this tile's end
+        Adj tl = lam;
+        if (W > 1) {
+            if (act && lane == 1) {
+                s_x[wv][0] = PQ.a;
+                s_x[wv][1] = PQ.b;
+                s_x[wv][2] = PQ.c;
+                s_x[wv][3] = PQ.d;
+                s_x[wv][4] = pd;
+                s_x[wv][5] = pf.l0;
+                s_x[wv][6] = pf.l1;
+                s_x[wv][7] = pf.lD;
+            }
+            if (act && lane == 0) {
+                s_x[wv][8] = Q.a;
+                s_x[wv][9] = Q.b;
+                s_x[wv][10] = Q.c;
+                s_x[wv][11] = Q.d;
+                s_x[wv][12] = qd;
+                s_x[wv][13] = f.l0;
+                s_x[wv][14] = f.l1;
+                s_x[wv][15] = f.lD;
+            }
+            __syncthreads();
+            // the round's incoming adjoint through the deeper tiles of the
+            // round (lane 0's chunk-start adjoint of each, in the previous
+            // tile's frame), then on through the round for the next one
+            Adj x = lam;
+            for (int u = 0; u < W; ++u) {
+                if (u == wv) tl = x;
+                const int tu = rt - u;
+                if (tu < 0) break;
+                const double *q = s_x[u];
+                Adj e1, c1;
+                e1.l0 = fma(x.l0, q[0], fma(x.l1, q[1], q[5]));
+                e1.l1 = fma(x.l0, q[2], fma(x.l1, q[3], q[6]));
+                e1.lD = fma(x.lD, q[4], q[7]);
+                c1.l0 = fma(e1.l0, q[8], fma(e1.l1, q[9], q[13]));
+                c1.l1 = fma(e1.l0, q[10], fma(e1.l1, q[11], q[14]));
+                c1.lD = fma(e1.lD, q[12], q[15]);
+                const int ex = (tu > 0) ? s_cexp[tu] : 0;
+                x.l0 = ldexp(c1.l0, -ex);
+                x.l1 = ldexp(c1.l1, -ex);
+                x.lD = ldexp(c1.lD, -2 * ex);
+            }
+            lam = x;
+        }
         // adjoint at this lane's chunk end: Psi_{l+1}(lambda_tile_end)
         Adj le;
         {
@@ -1180,11 +1322,11 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
             const double nf0 = __shfl_down(pf.l0, 1), nf1 = __shfl_down(pf.l1, 1);
             const double nfD = __shfl_down(pf.lD, 1);
             if (lane == 63) {
-                le = lam;
+                le = tl;
             } else {
-                le.l0 = fma(lam.l0, nq.a, fma(lam.l1, nq.b, nf0));
-                le.l1 = fma(lam.l0, nq.c, fma(lam.l1, nq.d, nf1));
-                le.lD = fma(lam.lD, nd, nfD);
+                le.l0 = fma(tl.l0, nq.a, fma(tl.l1, nq.b, nf0));
+                le.l1 = fma(tl.l0, nq.c, fma(tl.l1, nq.d, nf1));
+                le.lD = fma(tl.lD, nd, nfD);
             }
         }
         // adjoint at the lane's chunk start: lambda_end J_chunk + f_chunk
@@ -1237,7 +1379,7 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         le = lstart;
         // adjoint of this tile's start state, expressed for the previous tile's
         // (un-renormalised) end state
-        {
+        if (W == 1) {
             Adj ls{lane_read(le.l0, 0), lane_read(le.l1, 0), lane_read(le.lD, 0)};   // le = chunk-start adjoint
             const int ex = (t > 0) ? s_cexp[t] : 0;
             lam.l0 = ldexp(ls.l0, -ex);
@@ -1250,18 +1392,26 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
         // sample k is the right end of interface k-1 and the left end of
         // interface k.  Branch-free: the interface factors vanish outside
         // [1, S), so dL/dZ is zero for k >= S and only the store is guarded.
+        // the sample after this tile and its interface's factor: the previous
+        // tile's (W = 1), the neighbouring wavefront's, or for the round's
+        // deepest tile those kept from the last round
+        double zn_t = z_next, rn_t = rbar_next;
+        if (W > 1 && wv > 0) {
+            zn_t = s_z_w[wv - 1][pad8(0)];
+            rn_t = s_rho_w[wv - 1][pad8(0)];
+        }
 #pragma unroll 1
         for (int jj = 0; jj < C; ++jj) {
             const int i = jj * 64 + lane;
             const int k = t0 + i;
             const double zl = (i > 0) ? s_z[pad8(i - 1)] : zstart;
-            const double zr = (i + 1 < T) ? s_z[pad8(i + 1)] : z_next;
+            const double zr = (i + 1 < T) ? s_z[pad8(i + 1)] : zn_t;
             const double ql = s_rho[pad8(i)];
-            const double qr = (k + 1 < S) ? ((i + 1 < T) ? s_rho[pad8(i + 1)] : rbar_next) : 0.0;
+            const double qr = (k + 1 < S) ? ((i + 1 < T) ? s_rho[pad8(i + 1)] : rn_t) : 0.0;
             const double zb = fma(-qr, zr, ql * zl);
             // zbar is NULL when no volume gradient is wanted (nothing reads it)
-            if (zbar && k < S) zbar[obase + k] = (float)zb;
-            if (pose_part) {
+            if (zbar && k < S && act) zbar[obase + k] = (float)zb;
+            if (pose_part && act) {
                 // dL/dp = zb dZ/dp; dL/dR accumulates (s_k dir) outer dL/dp
                 const double sk = fma((double)k, ray.ds, ray.r0);
 #pragma unroll
@@ -1272,18 +1422,44 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
                 }
             }
         }
-        rbar_next = lane_read(s_rho[pad8(lane)], 0);
-        z_next = lane_read(s_z[pad8(lane)], 0);
+        if (W == 1) {
+            rbar_next = lane_read(s_rho[pad8(lane)], 0);
+            z_next = lane_read(s_z[pad8(lane)], 0);
+        } else {
+            // for the next round's deepest tile: this round's shallowest
+            rbar_next = s_rho_w[W - 1][pad8(0)];
+            z_next = s_z_w[W - 1][pad8(0)];
+        }
         __syncthreads();
     }
+    double r[6];
     if (pose_part) {
-        double r[6];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             r[a] = wave_sum(gsum[a]);
             r[3 + a] = wave_sum(gssum[a]);
         }
+    }
+    double ls = 0.0;
+    if (FUSED && loss_acc) ls = wave_sum(loss);
+    if (W > 1) {
+        // the wavefronts' shares added in a fixed order
         if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) s_red[wv][a] = pose_part ? r[a] : 0.0;
+            s_red[wv][6] = ls;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            for (int u = 1; u < W; ++u) {
+#pragma unroll
+                for (int a = 0; a < 6; ++a) r[a] += s_red[u][a];
+                ls += s_red[u][6];
+            }
+        }
+    }
+    if (pose_part) {
+        if (threadIdx.x == 0) {
             // this ray's share of dL/dt = sum g and dL/dR = sum g (s dir)^T,
             // dir = (sx, 0, cz); k_pose_reduce sums the rays of each pose
             // (in a fixed order: no contended atomics on the pose's entries)
@@ -1298,16 +1474,16 @@ __global__ __launch_bounds__(64) void k_backward(VolArgs v, PhysArgs p, FanTable
     }
     if (FUSED && loss_acc) {
         // one partial per ray, summed by k_sum_f64 (no contended atomics)
-        const double ls = wave_sum(loss);
-        if (lane == 0) loss_acc[g] = ls;
+        if (threadIdx.x == 0) loss_acc[g] = ls;
     }
 }
 
 // --------------------------------------------------------------------------
 // scatter of dL/dZ_k: trilinear weights into the volume gradient.  One
 // wavefront takes RB neighbouring rays of one fan (64/RB lanes per ray) and
-// one segment of `seg` depths (blockIdx.y), and walks them together in
-// groups of 256/RB depths; every lane owns 4 consecutive depths of its ray.
+// one segment of `seg` depths, and walks them together in groups of
+// (64/RB) spl depths; every lane owns spl (4, 2 or 1) consecutive depths of
+// its ray.
 // A straight ray meets each cell once, so a
 // lane's consecutive samples in one cell form a run that it sums in
 // registers before touching memory.  The stencils of a group fill a small
@@ -1331,7 +1507,7 @@ struct ScatterBox {
 template <int RB>
 __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const RayRec *__restrict__ rays,
                                                 const float *__restrict__ zbar, float *__restrict__ gZ,
-                                                int seg, int xgrp, unsigned long long *__restrict__ fix,
+                                                int seg_shift, int xgrp, unsigned long long *__restrict__ fix,
                                                 const double *__restrict__ fscale)
 {
     constexpr int LPR = 64 / RB;                 // lanes per ray
@@ -1346,20 +1522,29 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
     // lanes of one LDS atomic rarely meet in one cell
     constexpr int SH = LPR / RB;
     const int ch = (ll + slot * SH) % LPR;
-    // block -> (fan, first ray); each fan owns ceil(n_rays / RB) blocks
+    // block -> (fan, depth segment, first ray).  Each fan owns ceil(n_rays /
+    // RB) ray blocks.  One-dimensional grid: the fans one after the other,
+    // each with its ceil(n_samples / seg) segments of ray blocks (ray blocks
+    // fastest: neighbouring wavefronts share voxels).  Two-dimensional grid:
+    // the ray blocks of all fans along x, the segment along y (a fan's
+    // blocks past its depth exit at once).
     const int b = remap_block(blockIdx.x, gridDim.x, xgrp);
-    int fi = 0, acc = 0;
+    const bool two_d = gridDim.y > 1;
+    const int seg = 1 << seg_shift;              // a power of two: no division per fan
+    int fi = 0, acc = 0, nrb = 1;
     for (;; ++fi) {
-        const int nb = (tab.f[fi].n_rays + RB - 1) / RB;
+        nrb = (tab.f[fi].n_rays + RB - 1) / RB;
+        const int nb = two_d ? nrb : nrb * ((tab.f[fi].n_samples + seg - 1) >> seg_shift);
         if (b < acc + nb || fi + 1 == tab.n) break;
         acc += nb;
     }
     const FanRec fr = tab.f[fi];
-    const int j = (b - acc) * RB + slot;
+    const int sgi = two_d ? (int)blockIdx.y : (b - acc) / nrb;
+    const int j = (b - acc - (two_d ? 0 : sgi * nrb)) * RB + slot;
     const bool ray_ok = j < fr.n_rays;
     const int S = fr.n_samples;
-    const int k_begin = blockIdx.y * seg;
-    if (k_begin >= S) return;                   // whole wavefront: segment past this fan's depth
+    const int k_begin = sgi * seg;
+    if (k_begin >= S) return;                   // whole wavefront: past this fan's depth
     const int k_end = min(S, k_begin + seg);
     // RB rays per wavefront, their geometry as the adjoint set it up
     Ray ray;
@@ -2336,32 +2521,49 @@ inline int grid_for(long long n, int block)
     return (int)g;
 }
 
+// rays of the fans at the front of a table whose rays are walked by
+// kSpanWaves wavefronts each (a table lists its fans longest first)
+inline int span_rays(const FanTable &t, int span_samples)
+{
+    int n = 0;
+    if (span_samples <= 0) return 0;
+    for (int f = 0; f < t.n && t.f[f].n_samples >= span_samples; ++f) n += t.f[f].n_rays;
+    return n;
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------------
 // launch wrappers
 // --------------------------------------------------------------------------
+#define DUS_FWD_LAUNCH(CH, SPK, WV, NG, G0, ZERO)                                               \
+    hipLaunchKernelGGL((k_forward<CH, SPK, WV>), dim3(NG), dim3(64 * WV), 0, st, v, p, t, poses, out, \
+                       min_pivot, pivot_base, carry, carry_exp, cstate, gain, G0, xcd_group, ZERO)
+
 #define DUS_FWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
-        if (p.speckle)                                                                         \
-            hipLaunchKernelGGL((k_forward<CH, true>), dim3(grid), dim3(64), 0, st, v, p, t,    \
-                               poses, out, min_pivot, pivot_base, carry, carry_exp, cstate,    \
-                               gain,                                                           \
-                               xcd_group, zero);                                               \
-        else                                                                                   \
-            hipLaunchKernelGGL((k_forward<CH, false>), dim3(grid), dim3(64), 0, st, v, p, t,   \
-                               poses, out, min_pivot, pivot_base, carry, carry_exp, cstate,    \
-                               gain,                                                           \
-                               xcd_group, zero);                                               \
+        if (n_span > 0) {                                                                      \
+            if (p.speckle) DUS_FWD_LAUNCH(CH, true, kSpanWaves, n_span, 0, zero);              \
+            else DUS_FWD_LAUNCH(CH, false, kSpanWaves, n_span, 0, zero);                       \
+        }                                                                                      \
+        if (n_one > 0) {                                                                       \
+            if (p.speckle) DUS_FWD_LAUNCH(CH, true, 1, n_one, n_span, zero1);                  \
+            else DUS_FWD_LAUNCH(CH, false, 1, n_one, n_span, zero1);                           \
+        }                                                                                      \
         break;
 
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out, float *min_pivot,
                           int pivot_base, double *carry, int32_t *carry_exp, double *cstate, float *gain,
-                          hipStream_t st, const ZeroArgs &zero)
+                          hipStream_t st, const ZeroArgs &zero, int span_samples)
 {
-    const int grid = t.total_rays;
-    if (grid <= 0) return hipSuccess;
+    if (t.total_rays <= 0) return hipSuccess;
+    // the rays of the table's long fans (its first ones: a table lists its
+    // fans longest first) get kSpanWaves wavefronts each, the rest one
+    const int n_span = span_rays(t, span_samples);
+    const int n_one = t.total_rays - n_span;
+    // the clears go with the first launch
+    const ZeroArgs zero1 = (n_span > 0) ? ZeroArgs{} : zero;
     switch (chunk) {
         DUS_FWD_CASE(4)
         DUS_FWD_CASE(8)
@@ -2372,19 +2574,27 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
     return hipGetLastError();
 }
 
-#define DUS_BWD_LAUNCH(CH, SPK, FUSED)                                                          \
-    hipLaunchKernelGGL((k_backward<CH, SPK, FUSED>), dim3(grid), dim3(64), 0, st, v, p, t,      \
-                       poses, zbar ? rays : nullptr, gsrc, target, zbar, pose_acc ? pose_part : nullptr, loss, carry,           \
-                       carry_exp, cstate, gain, xcd_group)
+#define DUS_BWD_LAUNCH(CH, SPK, FUSED, WV, NG, G0)                                                \
+    hipLaunchKernelGGL((k_backward<CH, SPK, FUSED, WV>), dim3(NG), dim3(64 * WV), 0, st, v, p, t,      \
+                       poses, zbar ? rays : nullptr, gsrc, target, zbar, pose_acc ? pose_part : nullptr, \
+                       loss, carry, carry_exp, cstate, gain, G0, xcd_group)
 
+// the long rays (the table's first n_span) with the forward's hand-off take
+// kSpanWaves * 4 / C wavefronts each (the LDS of C = 8 holds half as many)
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
-        if (fused) {                                                                           \
-            if (spk) DUS_BWD_LAUNCH(CH, true, true);                                           \
-            else DUS_BWD_LAUNCH(CH, false, true);                                              \
-        } else {                                                                               \
-            if (spk) DUS_BWD_LAUNCH(CH, true, false);                                          \
-            else DUS_BWD_LAUNCH(CH, false, false);                                             \
+        if (n_span > 0) {                                                                      \
+            if (fused) DUS_BWD_LAUNCH(CH, false, true, kSpanWaves * 4 / CH, n_span, 0);        \
+            else DUS_BWD_LAUNCH(CH, false, false, kSpanWaves * 4 / CH, n_span, 0);             \
+        }                                                                                      \
+        if (n_one > 0) {                                                                       \
+            if (fused) {                                                                       \
+                if (spk) DUS_BWD_LAUNCH(CH, true, true, 1, n_one, n_span);                     \
+                else DUS_BWD_LAUNCH(CH, false, true, 1, n_one, n_span);                        \
+            } else {                                                                           \
+                if (spk) DUS_BWD_LAUNCH(CH, true, false, 1, n_one, n_span);                    \
+                else DUS_BWD_LAUNCH(CH, false, false, 1, n_one, n_span);                       \
+            }                                                                                  \
         }                                                                                      \
         break;
 
@@ -2392,15 +2602,18 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
                           const FanTable &t, const float *poses, RayRec *rays, const float *gsrc,
                           const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
-                          const float *gain, hipStream_t st)
+                          const float *gain, hipStream_t st, int span_samples)
 {
-    const int grid = t.total_rays;
-    if (grid <= 0) return hipSuccess;
+    if (t.total_rays <= 0) return hipSuccess;
     if (pose_acc && !pose_part) return hipErrorInvalidValue;
     if (zbar && !rays) return hipErrorInvalidValue;
     const bool fused = (target != nullptr);
     const bool spk = p.speckle && !gain;      // recorded gains replace the speckle variates
     if (!carry) cstate = nullptr;             // chunk states are read in the frames of the carry records
+    // several wavefronts per long ray need the forward's carry records and
+    // chunk states (and its gains, when there is speckle)
+    const int n_span = (carry && cstate && !spk) ? span_rays(t, span_samples) : 0;
+    const int n_one = t.total_rays - n_span;
     switch (chunk) {
         DUS_BWD_CASE(4)
         DUS_BWD_CASE(8)
@@ -2423,35 +2636,52 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
 {
     if (t.total_rays <= 0 || (!gZ && !fix)) return hipSuccess;
     if (!zbar || !rays || (fix && !fscale)) return hipErrorInvalidValue;
-    // 0: automatic.  Eight rays per wavefront, unless that leaves fewer than
-    // two wavefronts per SIMD; then two (more wavefronts, each walking a
-    // quarter as many groups)
-    if (scatter_rays == 0) scatter_rays = (t.total_rays / 8 < 2048) ? 2 : 8;
-    int blocks = 0, smax = 0;
+    // depth segments, the same power-of-two length for every fan, a whole
+    // number of the largest groups (256 / RB depths): the shortest that
+    // keeps the launch within about 32 wavefronts per SIMD (a wavefront's
+    // set-up is a few loads, so short segments cost little and even out the
+    // finishing times; a fan of long rays gets as many wavefronts per ray as
+    // its length asks for)
+    auto units = [&](int rb, int sg) {
+        long long u = 0;
+        for (int f = 0; f < t.n; ++f)
+            u += (long long)((t.f[f].n_rays + rb - 1) / rb) * ((t.f[f].n_samples + sg - 1) / sg);
+        return u;
+    };
+    // 0: automatic.  Eight rays per wavefront, unless even the shortest
+    // segments leave fewer than two wavefronts per SIMD; then two
+    if (scatter_rays == 0) scatter_rays = (units(8, 32) < 2048) ? 2 : 8;
+    int seg = 256 / scatter_rays, seg_shift = 0;
+    while (seg < DUS_MAX_SAMPLES && units(scatter_rays, seg) > 32768) seg *= 2;
+    while ((1 << seg_shift) < seg) ++seg_shift;
+    const long long nunits = units(scatter_rays, seg);
+    if (nunits <= 0) return hipSuccess;
+    if (nunits > INT32_MAX) return hipErrorInvalidValue;
+    // fans of different lengths run faster segment by segment (a 2-D grid,
+    // uneven 64-pose batch: 188 -> 178 us) unless most of that grid would be
+    // empty blocks (a few very long fans: 1-D); equal fans run faster fan by
+    // fan (bench step 144 -> 137 us)
+    long long nrb_all = 0;
+    int smax = 0;
     for (int f = 0; f < t.n; ++f) {
-        blocks += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
+        nrb_all += (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
         smax = std::max(smax, t.f[f].n_samples);
     }
-    if (blocks <= 0 || smax <= 0) return hipSuccess;
-    // depth segments: about 32 wavefronts per SIMD over the launch (a
-    // wavefront's set-up is a few loads, so short segments cost little and
-    // even out the finishing times), each segment a whole number of groups
-    const int G = 256 / scatter_rays;
-    const int ngroups = (smax + G - 1) / G;
-    const int nseg = std::max(1, std::min(ngroups, (32768 + blocks - 1) / blocks));
-    const int seg = ((ngroups + nseg - 1) / nseg) * G;
-    const dim3 grid(blocks, (smax + seg - 1) / seg);
+    const long long nseg_max = (smax + seg - 1) / seg;
+    const long long grid2 = nrb_all * nseg_max;
+    const dim3 grid = (grid2 > nunits && grid2 <= 2 * nunits) ? dim3((unsigned)nrb_all, (unsigned)nseg_max)
+                                                              : dim3((unsigned)nunits);
     switch (scatter_rays) {
     case 2:
-        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group,
+        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg_shift, xcd_group,
                            fix, fscale);
         break;
     case 4:
-        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group,
+        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg_shift, xcd_group,
                            fix, fscale);
         break;
     case 8:
-        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg, xcd_group,
+        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg_shift, xcd_group,
                            fix, fscale);
         break;
     default:

@@ -232,9 +232,9 @@ def pixel_gain(fan, phys, device) -> torch.Tensor:
     return out[:f.n_rays, :f.n_samples]
 
 
-def set_schedule(fwd_chunk=0, bwd_chunk=0, xcd_group=0, scatter_rays=0):
+def set_schedule(fwd_chunk=0, bwd_chunk=0, xcd_group=0, scatter_rays=0, span_samples=0):
     """Schedule of the direct render / adjoint calls (0 = library default)."""
-    s = DusSchedule(int(fwd_chunk), int(bwd_chunk), int(xcd_group), int(scatter_rays))
+    s = DusSchedule(int(fwd_chunk), int(bwd_chunk), int(xcd_group), int(scatter_rays), int(span_samples))
     check(_lib.lib().dus_set_schedule(ctypes.byref(s)), "dus_set_schedule")
 
 
@@ -242,7 +242,7 @@ def get_schedule() -> dict:
     s = DusSchedule()
     check(_lib.lib().dus_get_schedule(ctypes.byref(s)), "dus_get_schedule")
     return {"fwd_chunk": s.fwd_chunk, "bwd_chunk": s.bwd_chunk, "xcd_group": s.xcd_group,
-            "scatter_rays": s.scatter_rays}
+            "scatter_rays": s.scatter_rays, "span_samples": s.span_samples}
 
 
 def sample_volume(Z: torch.Tensor, poses: torch.Tensor, geom: Geometry, out: torch.Tensor | None = None):
@@ -370,15 +370,15 @@ class FusedStep:
         if schedule:
             self.set_schedule(**schedule)
 
-    def set_schedule(self, fwd_chunk=0, bwd_chunk=0, xcd_group=0, scatter_rays=0):
-        s = DusSchedule(int(fwd_chunk), int(bwd_chunk), int(xcd_group), int(scatter_rays))
+    def set_schedule(self, fwd_chunk=0, bwd_chunk=0, xcd_group=0, scatter_rays=0, span_samples=0):
+        s = DusSchedule(int(fwd_chunk), int(bwd_chunk), int(xcd_group), int(scatter_rays), int(span_samples))
         check(_lib.lib().dus_plan_set_schedule(self._h, ctypes.byref(s)), "dus_plan_set_schedule")
 
     def get_schedule(self) -> dict:
         s = DusSchedule()
         check(_lib.lib().dus_plan_get_schedule(self._h, ctypes.byref(s)), "dus_plan_get_schedule")
         return {"fwd_chunk": s.fwd_chunk, "bwd_chunk": s.bwd_chunk, "xcd_group": s.xcd_group,
-                "scatter_rays": s.scatter_rays}
+                "scatter_rays": s.scatter_rays, "span_samples": s.span_samples}
 
     def workspace(self, device) -> torch.Tensor:
         if self._ws is None or self._ws.device != torch.device(device):

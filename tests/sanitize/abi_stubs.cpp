@@ -119,7 +119,7 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t)
 
 namespace dus {
 hipError_t launch_forward(int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *, float *,
-                          float *, int, double *, int32_t *, double *, float *, hipStream_t, const ZeroArgs &)
+                          float *, int, double *, int32_t *, double *, float *, hipStream_t, const ZeroArgs &, int)
 {
     check_table(t);
     return hipSuccess;
@@ -133,7 +133,7 @@ hipError_t launch_backward(int, int, int, const VolArgs &, const PhysArgs &, con
 }
 hipError_t launch_adjoint(int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *, RayRec *,
                           const float *, const float *, float *, double *, double *, double *, const double *,
-                          const int32_t *, const double *, const float *, hipStream_t)
+                          const int32_t *, const double *, const float *, hipStream_t, int)
 {
     check_table(t);
     return hipSuccess;

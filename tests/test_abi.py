@@ -198,15 +198,17 @@ def test_schedule_validation():
     old = _lib.DusSchedule()
     assert L.dus_get_schedule(ctypes.byref(old)) == _lib.DUS_OK
     try:
-        for bad in [(3, 0, 0, 0), (0, 16, 0, 0), (0, 0, 65, 0), (0, 0, 0, 3), (0, 0, 0, 16)]:
+        for bad in [(3, 0, 0, 0, 0), (0, 16, 0, 0, 0), (0, 0, 65, 0, 0), (0, 0, 0, 3, 0), (0, 0, 0, 16, 0),
+                    (0, 0, 0, 0, -2), (0, 0, 0, 0, _lib.MAX_SAMPLES + 1)]:
             assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(*bad))) == _lib.DUS_EINVAL, bad
-        assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(0, 0, 0, 0))) == _lib.DUS_OK
+        assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(0, 0, 0, 0, 0))) == _lib.DUS_OK
         got = _lib.DusSchedule()
         assert L.dus_get_schedule(ctypes.byref(got)) == _lib.DUS_OK
-        assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays) == (8, 4, 16, 0)
-        assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(16, 8, 64, 2))) == _lib.DUS_OK
-        assert L.dus_get_schedule(ctypes.byref(got)) == _lib.DUS_OK
-        assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays) == (16, 8, 64, 2)
+        assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays, got.span_samples) == (8, 4, 16, 0, 4096)
+        for span in (-1, 1, _lib.MAX_SAMPLES):
+            assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(16, 8, 64, 2, span))) == _lib.DUS_OK
+            assert L.dus_get_schedule(ctypes.byref(got)) == _lib.DUS_OK
+            assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays, got.span_samples) == (16, 8, 64, 2, span)
     finally:
         L.dus_set_schedule(ctypes.byref(old))
 
