@@ -247,6 +247,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--step-only", action="store_true",
+                    help="skip the uneven and skewed batches (profiling runs: every launch at the step's "
+                         "grid then belongs to the step)")
     ap.add_argument("--tune-cache", default="", help="reuse / store the tuned schedule in this JSON file")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also launch a plain device copy of 512 MiB (counter calibration)")
@@ -377,12 +380,14 @@ def main():
              "scan_convert_512x512": {"ms": ms_scan}}
     log(f"bench: modes {json.dumps(modes)}")
 
-    log("bench: uneven 64-pose batch")
-    uneven = uneven_batch(Z, dev, max(5, args.steps // 2), not args.no_plain, ev)
-    log(f"bench: uneven batch {json.dumps(uneven)}")
-    log("bench: skewed batch")
-    skewed = skewed_batch(Z, dev, max(5, args.steps // 2), ev)
-    log(f"bench: skewed batch {json.dumps(skewed)}")
+    uneven = skewed = None
+    if not args.step_only:
+        log("bench: uneven 64-pose batch")
+        uneven = uneven_batch(Z, dev, max(5, args.steps // 2), not args.no_plain, ev)
+        log(f"bench: uneven batch {json.dumps(uneven)}")
+        log("bench: skewed batch")
+        skewed = skewed_batch(Z, dev, max(5, args.steps // 2), ev)
+        log(f"bench: skewed batch {json.dumps(skewed)}")
 
     if args.calib_copy:
         src = torch.empty(CALIB_BYTES // 4, device=dev).fill_(1.0)
