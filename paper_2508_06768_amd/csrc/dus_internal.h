@@ -55,7 +55,8 @@ struct FanTable {
     int32_t n;              // fans in this launch
     int32_t total_rays;
     int32_t total_blur_blocks;
-    int32_t pad_;
+    int32_t ray0;           // forward and adjoint, one wavefront per ray: rays below ray0 are
+                            // another launch's (their wavefronts return at once)
     FanRec f[kMaxFans];
 };
 

@@ -450,9 +450,11 @@ __device__ __forceinline__ float posthoc_coef(const PhysArgs &p, float ds)
 // --------------------------------------------------------------------------
 // phase 1: gather samples [t0, t0+T) of a ray, interface rho of (k-1, k)
 // into s_rho[pad8(k - t0)]; optionally keep the samples in s_z, and the
-// last sample of every 256-sample block in s_zc (tile carries).
+// last sample of every 256-sample block in s_zc (tile carries).  W (the
+// caller's wavefronts per ray) only keeps the callers' instances apart: the
+// compiler then derives each caller's index ranges from that caller alone.
 // --------------------------------------------------------------------------
-template <int C, bool KEEPZ, bool KEEPG, bool INSIDE>
+template <int C, bool KEEPZ, bool KEEPG, bool INSIDE, int W>
 __device__ __forceinline__ void gather_tile_body(const VolArgs &v, const Ray &ray, int t0, int S,
                                                  bool absm, int lane, double &zprev, double *s_rho,
                                                  double *s_z, float *s_g, double *s_zc, double *s_dq)
@@ -502,7 +504,7 @@ __device__ __forceinline__ void gather_tile_body(const VolArgs &v, const Ray &ra
     }
 }
 
-template <int C, bool KEEPZ, bool KEEPG = false>
+template <int C, bool KEEPZ, bool KEEPG = false, int W = 1>
 __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, int t0, int S,
                                             bool absm, int lane, double &zprev, double *s_rho,
                                             double *s_z, float *s_g = nullptr, double *s_zc = nullptr,
@@ -511,9 +513,9 @@ __device__ __forceinline__ void gather_tile(const VolArgs &v, const Ray &ray, in
     // a tile whose samples all lie inside the volume skips the clamps (the
     // ray is the same on every lane, so the branch is uniform)
     if (segment_inside(v, ray, t0, min(t0 + 64 * C - 1, S - 1)))
-        gather_tile_body<C, KEEPZ, KEEPG, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, s_zc, s_dq);
+        gather_tile_body<C, KEEPZ, KEEPG, true, W>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, s_zc, s_dq);
     else
-        gather_tile_body<C, KEEPZ, KEEPG, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, s_zc, s_dq);
+        gather_tile_body<C, KEEPZ, KEEPG, false, W>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, s_zc, s_dq);
 }
 
 // transfer map of interface rho (first column and determinant; the second
@@ -644,7 +646,7 @@ __global__ __launch_bounds__(64 * W) void k_forward(VolArgs v, PhysArgs p, FanTa
                                                     int pivot_base, double *__restrict__ carry,
                                                     int32_t *__restrict__ carry_exp,
                                                     double *__restrict__ cstate,
-                                                    float *__restrict__ gain_out, int g0, int xgrp, ZeroArgs zero)
+                                                    float *__restrict__ gain_out, int xgrp, ZeroArgs zero)
 {
     constexpr int T = 64 * C;
     static_assert(T % kCarryBlock == 0, "tiles hold whole carry blocks");
@@ -677,7 +679,8 @@ __global__ __launch_bounds__(64 * W) void k_forward(VolArgs v, PhysArgs p, FanTa
         }
         for (long long i = i0; i < zero.nb; i += stride) zero.b[i] = 0.0;
     }
-    const int g = g0 + remap_block(blockIdx.x, gridDim.x, xgrp);
+    const int g = remap_block(blockIdx.x, gridDim.x, xgrp);
+    if (W == 1 && g < tab.ray0) return;          // walked by several wavefronts in another launch
     const int fi = find_fan(tab, g);
     const FanRec fr = tab.f[fi];
     const int j = g - fr.ray_begin;
@@ -708,7 +711,7 @@ __global__ __launch_bounds__(64 * W) void k_forward(VolArgs v, PhysArgs p, FanTa
         }
         const double zstart = zprev;
         if (act) {
-            gather_tile<C, false>(v, ray, t0, S, absm, lane, zprev, s_rho, nullptr, nullptr,
+            gather_tile<C, false, false, W>(v, ray, t0, S, absm, lane, zprev, s_rho, nullptr, nullptr,
                                   carry ? s_zc : nullptr);
             if (SPK) speckle_radial<T>(p, t0, j, fr.speckle_id, lane, s_xir);
         }
@@ -953,7 +956,7 @@ __global__ __launch_bounds__(64 * W) void k_backward(VolArgs v, PhysArgs p, FanT
                                                  const double *__restrict__ carry,
                                                  const int32_t *__restrict__ carry_exp,
                                                  const double *__restrict__ cstate,
-                                                 const float *__restrict__ gain_in, int g0, int xgrp)
+                                                 const float *__restrict__ gain_in, int xgrp)
 {
     constexpr int T = 64 * C;
     constexpr int kMaxTiles = (DUS_MAX_SAMPLES + T - 1) / T;
@@ -983,7 +986,8 @@ __global__ __launch_bounds__(64 * W) void k_backward(VolArgs v, PhysArgs p, FanT
     double *s_dq = s_dq_w[wv];
     float *s_eb = s_eb_w[wv];
     float *s_gain = s_gain_w[wv];
-    const int g = g0 + remap_block(blockIdx.x, gridDim.x, xgrp);
+    const int g = remap_block(blockIdx.x, gridDim.x, xgrp);
+    if (W == 1 && g < tab.ray0) return;          // walked by several wavefronts in another launch
     const int fi = find_fan(tab, g);
     const FanRec fr = tab.f[fi];
     const int j = g - fr.ray_begin;
@@ -1115,9 +1119,9 @@ __global__ __launch_bounds__(64 * W) void k_backward(VolArgs v, PhysArgs p, FanT
             }
         }
         if (pose_part)
-            gather_tile<C, true, true>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, nullptr, s_dq);
+            gather_tile<C, true, true, W>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, s_g, nullptr, s_dq);
         else
-            gather_tile<C, true, false>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, nullptr, nullptr, s_dq);
+            gather_tile<C, true, false, W>(v, ray, t0, S, absm, lane, zprev, s_rho, s_z, nullptr, nullptr, s_dq);
         if (SPK) speckle_fill<T>(p, t0, j, fr.speckle_id, lane, s_xig, s_xir);
         __syncthreads();
         // dL/de (or the target for the fused loss) staged through LDS: the C
@@ -2536,19 +2540,19 @@ inline int span_rays(const FanTable &t, int span_samples)
 // --------------------------------------------------------------------------
 // launch wrappers
 // --------------------------------------------------------------------------
-#define DUS_FWD_LAUNCH(CH, SPK, WV, NG, G0, ZERO)                                               \
-    hipLaunchKernelGGL((k_forward<CH, SPK, WV>), dim3(NG), dim3(64 * WV), 0, st, v, p, t, poses, out, \
-                       min_pivot, pivot_base, carry, carry_exp, cstate, gain, G0, xcd_group, ZERO)
+#define DUS_FWD_LAUNCH(CH, SPK, WV, NG, TAB, ZERO)                                              \
+    hipLaunchKernelGGL((k_forward<CH, SPK, WV>), dim3(NG), dim3(64 * WV), 0, st, v, p, TAB, poses, out, \
+                       min_pivot, pivot_base, carry, carry_exp, cstate, gain, xcd_group, ZERO)
 
 #define DUS_FWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
         if (n_span > 0) {                                                                      \
-            if (p.speckle) DUS_FWD_LAUNCH(CH, true, kSpanWaves, n_span, 0, zero);              \
-            else DUS_FWD_LAUNCH(CH, false, kSpanWaves, n_span, 0, zero);                       \
+            if (p.speckle) DUS_FWD_LAUNCH(CH, true, kSpanWaves, n_span, t, zero);              \
+            else DUS_FWD_LAUNCH(CH, false, kSpanWaves, n_span, t, zero);                       \
         }                                                                                      \
         if (n_one > 0) {                                                                       \
-            if (p.speckle) DUS_FWD_LAUNCH(CH, true, 1, n_one, n_span, zero1);                  \
-            else DUS_FWD_LAUNCH(CH, false, 1, n_one, n_span, zero1);                           \
+            if (p.speckle) DUS_FWD_LAUNCH(CH, true, 1, t.total_rays, t1, zero1);                      \
+            else DUS_FWD_LAUNCH(CH, false, 1, t.total_rays, t1, zero1);                               \
         }                                                                                      \
         break;
 
@@ -2564,6 +2568,8 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
     const int n_one = t.total_rays - n_span;
     // the clears go with the first launch
     const ZeroArgs zero1 = (n_span > 0) ? ZeroArgs{} : zero;
+    FanTable t1 = t;
+    t1.ray0 = n_span;
     switch (chunk) {
         DUS_FWD_CASE(4)
         DUS_FWD_CASE(8)
@@ -2574,26 +2580,26 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
     return hipGetLastError();
 }
 
-#define DUS_BWD_LAUNCH(CH, SPK, FUSED, WV, NG, G0)                                                \
-    hipLaunchKernelGGL((k_backward<CH, SPK, FUSED, WV>), dim3(NG), dim3(64 * WV), 0, st, v, p, t,      \
+#define DUS_BWD_LAUNCH(CH, SPK, FUSED, WV, NG, TAB)                                               \
+    hipLaunchKernelGGL((k_backward<CH, SPK, FUSED, WV>), dim3(NG), dim3(64 * WV), 0, st, v, p, TAB,    \
                        poses, zbar ? rays : nullptr, gsrc, target, zbar, pose_acc ? pose_part : nullptr, \
-                       loss, carry, carry_exp, cstate, gain, G0, xcd_group)
+                       loss, carry, carry_exp, cstate, gain, xcd_group)
 
 // the long rays (the table's first n_span) with the forward's hand-off take
 // kSpanWaves * 4 / C wavefronts each (the LDS of C = 8 holds half as many)
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
         if (n_span > 0) {                                                                      \
-            if (fused) DUS_BWD_LAUNCH(CH, false, true, kSpanWaves * 4 / CH, n_span, 0);        \
-            else DUS_BWD_LAUNCH(CH, false, false, kSpanWaves * 4 / CH, n_span, 0);             \
+            if (fused) DUS_BWD_LAUNCH(CH, false, true, kSpanWaves * 4 / CH, n_span, t);        \
+            else DUS_BWD_LAUNCH(CH, false, false, kSpanWaves * 4 / CH, n_span, t);             \
         }                                                                                      \
         if (n_one > 0) {                                                                       \
             if (fused) {                                                                       \
-                if (spk) DUS_BWD_LAUNCH(CH, true, true, 1, n_one, n_span);                     \
-                else DUS_BWD_LAUNCH(CH, false, true, 1, n_one, n_span);                        \
+                if (spk) DUS_BWD_LAUNCH(CH, true, true, 1, t.total_rays, t1);                     \
+                else DUS_BWD_LAUNCH(CH, false, true, 1, t.total_rays, t1);                        \
             } else {                                                                           \
-                if (spk) DUS_BWD_LAUNCH(CH, true, false, 1, n_one, n_span);                    \
-                else DUS_BWD_LAUNCH(CH, false, false, 1, n_one, n_span);                       \
+                if (spk) DUS_BWD_LAUNCH(CH, true, false, 1, t.total_rays, t1);                    \
+                else DUS_BWD_LAUNCH(CH, false, false, 1, t.total_rays, t1);                       \
             }                                                                                  \
         }                                                                                      \
         break;
@@ -2614,6 +2620,8 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
     // chunk states (and its gains, when there is speckle)
     const int n_span = (carry && cstate && !spk) ? span_rays(t, span_samples) : 0;
     const int n_one = t.total_rays - n_span;
+    FanTable t1 = t;
+    t1.ray0 = n_span;
     switch (chunk) {
         DUS_BWD_CASE(4)
         DUS_BWD_CASE(8)
