@@ -339,8 +339,10 @@ int dus_get_schedule(dus_schedule *sched);
  * records and the physics (all HOST, copied into the plan) are validated as
  * for dus_render_bmode, and flags is a combination of DUS_PLAN_*.  *out
  * receives the plan (NULL on failure); the caller destroys it with
- * dus_plan_destroy.  Creating a plan allocates host memory and one HIP
- * stream for graph capture on the current device, never device memory.
+ * dus_plan_destroy.  Creating a plan allocates host memory, two HIP streams
+ * (graph capture; the launches of rays of at least span_samples samples,
+ * forked from and joined back into the step's stream) and two events on the
+ * current device, never device memory.
  */
 int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans,
                     int32_t n_poses, const dus_physics *phys, int32_t flags);

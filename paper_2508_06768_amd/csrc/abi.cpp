@@ -370,13 +370,15 @@ int make_sched(const dus_schedule *sc, Sched &n)
 int enqueue_forward(const Sched &sc, const dus::VolArgs &va, const dus::PhysArgs &pa,
                     const std::vector<dus::FanTable> &tabs, const float *poses, float *out,
                     float *min_pivot, hipStream_t st, double *carry = nullptr, int32_t *carry_exp = nullptr,
-                    double *cstate = nullptr, float *gain = nullptr, const dus::ZeroArgs &zero = dus::ZeroArgs{})
+                    double *cstate = nullptr, float *gain = nullptr, const dus::ZeroArgs &zero = dus::ZeroArgs{},
+                    const dus::SideStream *side = nullptr)
 {
     bool first = true;
     for (const auto &t : tabs) {
         if (t.total_rays <= 0) continue;
         DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, out, min_pivot, 0, carry,
-                                    carry_exp, cstate, gain, st, first ? zero : dus::ZeroArgs{}, sc.span_samples),
+                                    carry_exp, cstate, gain, st, first ? zero : dus::ZeroArgs{}, sc.span_samples,
+                                    side),
                 "forward kernel launch");
         first = false;
     }
@@ -395,6 +397,9 @@ struct dus_plan {
     WsLayout ws;
     int64_t extent;
     hipStream_t cap = nullptr;
+    // second stream (and its fork and join events) for the launches of long
+    // rays, which then run beside the one-wavefront launches
+    dus::SideStream side{};
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     const void *key[9] = {};
@@ -721,9 +726,12 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, 
     p->extent = image_extent(fans, n_poses);
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side.st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->side.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->side.join, hipEventDisableTiming);
     if (e != hipSuccess) {
-        delete p;
-        return hip_fail(e, "plan stream");
+        dus_plan_destroy(p);
+        return hip_fail(e, "plan streams and events");
     }
     *out = p;
     return DUS_OK;
@@ -837,7 +845,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         int s;
         float *img = blur ? reinterpret_cast<float *>((char *)ws + p->ws.pre) : bmode;
         if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, img, nullptr, st, car, cex, cst, gain,
-                                 fwd_clears ? zero : dus::ZeroArgs{})) != DUS_OK)
+                                 fwd_clears ? zero : dus::ZeroArgs{}, &p->side)) != DUS_OK)
             return s;
     }
     DUS_HIP(mark(DUS_PHASE_BLUR_LOSS), "event");
@@ -867,7 +875,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
                                         grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0,
                                         (!blur && loss) ? part + n_part : nullptr,
                                         fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? cst : nullptr,
-                                        fwd ? gain : nullptr, st, sc.span_samples),
+                                        fwd ? gain : nullptr, st, sc.span_samples, &p->side),
                     "adjoint kernel");
             if (!blur) n_part += t.total_rays;
             r0 += t.total_rays;
@@ -976,6 +984,9 @@ void dus_plan_destroy(dus_plan *p)
     if (!p) return;
     plan_drop_graph(p);
     if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->side.st) (void)hipStreamDestroy(p->side.st);
+    if (p->side.fork) (void)hipEventDestroy(p->side.fork);
+    if (p->side.join) (void)hipEventDestroy(p->side.join);
     delete p;
 }
 

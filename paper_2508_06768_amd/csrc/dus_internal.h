@@ -98,6 +98,14 @@ constexpr int kRayPart = 9;
 // cstate: optional chunk states (kStateDoubles per carry record; needs carry);
 // gain: optional per-pixel gain (speckle x post-hoc attenuation) output
 // Buffers a kernel clears on the side (a[0..na) and b[0..nb) set to zero)
+// A second stream for the launch of the long rays (several wavefronts per
+// ray), forked from and joined back into the launch stream with two events,
+// so that it runs beside the one-wavefront launch of the other rays.
+struct SideStream {
+    hipStream_t st;
+    hipEvent_t fork, join;
+};
+
 struct ZeroArgs {
     float *a;
     long long na;
@@ -111,7 +119,7 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
                           const FanTable &t, const float *poses, float *out,
                           float *min_pivot, int pivot_base, double *carry, int32_t *carry_exp,
                           double *cstate, float *gain, hipStream_t st, const ZeroArgs &zero = ZeroArgs{},
-                          int span_samples = kSpanSamples);
+                          int span_samples = kSpanSamples, const SideStream *side = nullptr);
 // adjoint: dL/dZ per sample into zbar (image layout), then its scatter; in
 // the fused form (target given) loss receives one partial per ray.  With
 // pose_acc (a flag here), pose_part receives kRayPart doubles per ray of the
@@ -130,7 +138,8 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
                           const FanTable &t, const float *poses, RayRec *rays, const float *gsrc,
                           const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
-                          const float *gain, hipStream_t st, int span_samples = kSpanSamples);
+                          const float *gain, hipStream_t st, int span_samples = kSpanSamples,
+                          const SideStream *side = nullptr);
 // pose_acc[pose] += the sum of the table's per-ray partials, one wavefront
 // per fan (fixed order)
 hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double *pose_acc, hipStream_t st);

@@ -2535,41 +2535,62 @@ inline int span_rays(const FanTable &t, int span_samples)
     return n;
 }
 
+// the side stream starts after what st has queued; st waits for it at the
+// join (graph capture turns both into graph edges)
+inline hipError_t fork_side(hipStream_t st, const SideStream &s)
+{
+    hipError_t e = hipEventRecord(s.fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s.st, s.fork, 0);
+    return e;
+}
+
+inline hipError_t join_side(hipStream_t st, const SideStream &s)
+{
+    hipError_t e = hipEventRecord(s.join, s.st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, s.join, 0);
+    return e;
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------------
 // launch wrappers
 // --------------------------------------------------------------------------
-#define DUS_FWD_LAUNCH(CH, SPK, WV, NG, TAB, ZERO)                                              \
-    hipLaunchKernelGGL((k_forward<CH, SPK, WV>), dim3(NG), dim3(64 * WV), 0, st, v, p, TAB, poses, out, \
+#define DUS_FWD_LAUNCH(CH, SPK, WV, NG, TAB, ZERO, STR)                                         \
+    hipLaunchKernelGGL((k_forward<CH, SPK, WV>), dim3(NG), dim3(64 * WV), 0, STR, v, p, TAB, poses, out, \
                        min_pivot, pivot_base, carry, carry_exp, cstate, gain, xcd_group, ZERO)
 
 #define DUS_FWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
         if (n_span > 0) {                                                                      \
-            if (p.speckle) DUS_FWD_LAUNCH(CH, true, kSpanWaves, n_span, t, zero);              \
-            else DUS_FWD_LAUNCH(CH, false, kSpanWaves, n_span, t, zero);                       \
+            if (p.speckle) DUS_FWD_LAUNCH(CH, true, kSpanWaves, n_span, t, ZeroArgs{}, sst);    \
+            else DUS_FWD_LAUNCH(CH, false, kSpanWaves, n_span, t, ZeroArgs{}, sst);             \
         }                                                                                      \
-        if (n_one > 0) {                                                                       \
-            if (p.speckle) DUS_FWD_LAUNCH(CH, true, 1, t.total_rays, t1, zero1);                      \
-            else DUS_FWD_LAUNCH(CH, false, 1, t.total_rays, t1, zero1);                               \
+        if (n_one > 0 || zero.na > 0 || zero.nb > 0) {                                         \
+            if (p.speckle) DUS_FWD_LAUNCH(CH, true, 1, t.total_rays, t1, zero, st);            \
+            else DUS_FWD_LAUNCH(CH, false, 1, t.total_rays, t1, zero, st);                     \
         }                                                                                      \
         break;
 
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out, float *min_pivot,
                           int pivot_base, double *carry, int32_t *carry_exp, double *cstate, float *gain,
-                          hipStream_t st, const ZeroArgs &zero, int span_samples)
+                          hipStream_t st, const ZeroArgs &zero, int span_samples, const SideStream *side)
 {
     if (t.total_rays <= 0) return hipSuccess;
     // the rays of the table's long fans (its first ones: a table lists its
     // fans longest first) get kSpanWaves wavefronts each, the rest one
     const int n_span = span_rays(t, span_samples);
     const int n_one = t.total_rays - n_span;
-    // the clears go with the first launch
-    const ZeroArgs zero1 = (n_span > 0) ? ZeroArgs{} : zero;
+    // the clears go with the one-wavefront launch (it covers every ray)
     FanTable t1 = t;
     t1.ray0 = n_span;
+    hipStream_t sst = st;
+    if (n_span > 0 && side) {
+        hipError_t e = fork_side(st, *side);
+        if (e != hipSuccess) return e;
+        sst = side->st;
+    }
     switch (chunk) {
         DUS_FWD_CASE(4)
         DUS_FWD_CASE(8)
@@ -2577,11 +2598,13 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
     default:
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && sst != st) e = join_side(st, *side);
+    return e;
 }
 
-#define DUS_BWD_LAUNCH(CH, SPK, FUSED, WV, NG, TAB)                                               \
-    hipLaunchKernelGGL((k_backward<CH, SPK, FUSED, WV>), dim3(NG), dim3(64 * WV), 0, st, v, p, TAB,    \
+#define DUS_BWD_LAUNCH(CH, SPK, FUSED, WV, NG, TAB, STR)                                          \
+    hipLaunchKernelGGL((k_backward<CH, SPK, FUSED, WV>), dim3(NG), dim3(64 * WV), 0, STR, v, p, TAB,   \
                        poses, zbar ? rays : nullptr, gsrc, target, zbar, pose_acc ? pose_part : nullptr, \
                        loss, carry, carry_exp, cstate, gain, xcd_group)
 
@@ -2590,16 +2613,16 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
 #define DUS_BWD_CASE(CH)                                                                       \
     case CH:                                                                                   \
         if (n_span > 0) {                                                                      \
-            if (fused) DUS_BWD_LAUNCH(CH, false, true, kSpanWaves * 4 / CH, n_span, t);        \
-            else DUS_BWD_LAUNCH(CH, false, false, kSpanWaves * 4 / CH, n_span, t);             \
+            if (fused) DUS_BWD_LAUNCH(CH, false, true, kSpanWaves * 4 / CH, n_span, t, sst);        \
+            else DUS_BWD_LAUNCH(CH, false, false, kSpanWaves * 4 / CH, n_span, t, sst);             \
         }                                                                                      \
         if (n_one > 0) {                                                                       \
             if (fused) {                                                                       \
-                if (spk) DUS_BWD_LAUNCH(CH, true, true, 1, t.total_rays, t1);                     \
-                else DUS_BWD_LAUNCH(CH, false, true, 1, t.total_rays, t1);                        \
+                if (spk) DUS_BWD_LAUNCH(CH, true, true, 1, t.total_rays, t1, st);                     \
+                else DUS_BWD_LAUNCH(CH, false, true, 1, t.total_rays, t1, st);                        \
             } else {                                                                           \
-                if (spk) DUS_BWD_LAUNCH(CH, true, false, 1, t.total_rays, t1);                    \
-                else DUS_BWD_LAUNCH(CH, false, false, 1, t.total_rays, t1);                       \
+                if (spk) DUS_BWD_LAUNCH(CH, true, false, 1, t.total_rays, t1, st);                    \
+                else DUS_BWD_LAUNCH(CH, false, false, 1, t.total_rays, t1, st);                       \
             }                                                                                  \
         }                                                                                      \
         break;
@@ -2608,7 +2631,7 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
                           const FanTable &t, const float *poses, RayRec *rays, const float *gsrc,
                           const float *target, float *zbar, double *pose_acc, double *pose_part, double *loss,
                           const double *carry, const int32_t *carry_exp, const double *cstate,
-                          const float *gain, hipStream_t st, int span_samples)
+                          const float *gain, hipStream_t st, int span_samples, const SideStream *side)
 {
     if (t.total_rays <= 0) return hipSuccess;
     if (pose_acc && !pose_part) return hipErrorInvalidValue;
@@ -2622,13 +2645,21 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
     const int n_one = t.total_rays - n_span;
     FanTable t1 = t;
     t1.ray0 = n_span;
+    hipStream_t sst = st;
+    if (n_span > 0 && side) {
+        hipError_t e = fork_side(st, *side);
+        if (e != hipSuccess) return e;
+        sst = side->st;
+    }
     switch (chunk) {
         DUS_BWD_CASE(4)
         DUS_BWD_CASE(8)
     default:
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && sst != st) e = join_side(st, *side);
+    return e;
 }
 
 hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double *pose_acc, hipStream_t st)

@@ -32,6 +32,15 @@ void drop(void *p)
     delete reinterpret_cast<Obj *>(p);
 }
 
+// a plan hands the launchers its side stream and both events, all created
+void check_side(const dus::SideStream *side)
+{
+    if (side && (!side->st || !side->fork || !side->join)) {
+        fprintf(stderr, "side stream or its events missing\n");
+        abort();
+    }
+}
+
 void check_table(const dus::FanTable &t)
 {
     ++g_launches;
@@ -103,6 +112,11 @@ hipError_t hipEventCreate(hipEvent_t *e)
     *e = make<hipEvent_t>(4);
     return hipSuccess;
 }
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned)
+{
+    *e = make<hipEvent_t>(4);
+    return hipSuccess;
+}
 hipError_t hipEventDestroy(hipEvent_t e)
 {
     drop(e);
@@ -119,8 +133,10 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t)
 
 namespace dus {
 hipError_t launch_forward(int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *, float *,
-                          float *, int, double *, int32_t *, double *, float *, hipStream_t, const ZeroArgs &, int)
+                          float *, int, double *, int32_t *, double *, float *, hipStream_t, const ZeroArgs &, int,
+                          const SideStream *side)
 {
+    check_side(side);
     check_table(t);
     return hipSuccess;
 }
@@ -133,8 +149,9 @@ hipError_t launch_backward(int, int, int, const VolArgs &, const PhysArgs &, con
 }
 hipError_t launch_adjoint(int, int, const VolArgs &, const PhysArgs &, const FanTable &t, const float *, RayRec *,
                           const float *, const float *, float *, double *, double *, double *, const double *,
-                          const int32_t *, const double *, const float *, hipStream_t, int)
+                          const int32_t *, const double *, const float *, hipStream_t, int, const SideStream *side)
 {
+    check_side(side);
     check_table(t);
     return hipSuccess;
 }
