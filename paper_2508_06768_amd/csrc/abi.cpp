@@ -165,7 +165,7 @@ dus::PhysArgs phys_args(const dus_physics *p)
 
 // Fan tables of at most kMaxFans fans, each sorted longest ray first so the
 // hardware dispatcher starts the longest rays first.
-std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses)
+std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses, int max_fans = dus::kMaxFans)
 {
     std::vector<int> pivot_begin(n_poses + 1, 0);
     for (int i = 0; i < n_poses; ++i) pivot_begin[i + 1] = pivot_begin[i] + std::max(0, fans[i].n_rays);
@@ -174,8 +174,8 @@ std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses)
         if (fans[i].n_rays > 0 && fans[i].n_samples > 0) order.push_back(i);
     std::vector<dus::FanTable> out;
     int64_t carries = 0;    // tile-carry records of all tables before this fan
-    for (size_t g0 = 0; g0 < order.size(); g0 += dus::kMaxFans) {
-        std::vector<int> grp(order.begin() + g0, order.begin() + std::min(order.size(), g0 + dus::kMaxFans));
+    for (size_t g0 = 0; g0 < order.size(); g0 += (size_t)max_fans) {
+        std::vector<int> grp(order.begin() + g0, order.begin() + std::min(order.size(), g0 + (size_t)max_fans));
         std::stable_sort(grp.begin(), grp.end(),
                          [&](int a, int b) { return fans[a].n_samples > fans[b].n_samples; });
         dus::FanTable t;
@@ -275,10 +275,16 @@ WsLayout layout(const dus_fan *fans, int32_t n_poses, const dus_physics *p, int 
         }
     }
     if (mode == 2) {
-        // one partial per blur block or per ray of every table
+        // one partial per blur block or per ray of every table: at most the
+        // larger of the two for every fan, however the fans are grouped in
+        // tables (a plan regroups them when its schedule changes)
         size_t n = 0;
-        for (const auto &t : build_tables(fans, n_poses))
-            n += (size_t)std::max(t.total_blur_blocks, t.total_rays);
+        for (int32_t i = 0; i < n_poses; ++i) {
+            const dus_fan &f = fans[i];
+            if (f.n_rays <= 0 || f.n_samples <= 0) continue;
+            const size_t bb = (size_t)((f.n_samples + 63) / 64) * (size_t)((f.n_rays + 63) / 64);
+            n += std::max(bb, (size_t)f.n_rays);
+        }
         L.part = off;
         L.part_bytes = std::max<size_t>(n, 1) * sizeof(double);
         off = align_up(off + L.part_bytes);
@@ -397,15 +403,41 @@ struct dus_plan {
     WsLayout ws;
     int64_t extent;
     hipStream_t cap = nullptr;
-    // second stream (and its fork and join events) for the launches of long
-    // rays, which then run beside the one-wavefront launches
+    // second stream, forked from the step's stream and joined back into it:
+    // the second chain of launches (half the tables), or, when some ray is
+    // long, the launches of the long rays beside the one-wavefront ones
     dus::SideStream side{};
+    hipEvent_t cleared = nullptr;   // the first table's forward has cleared dL/dZ and the pose sums
+    int max_fans = dus::kMaxFans;   // fans per table (two chains: half the fans each)
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     const void *key[9] = {};
     size_t key_ws_bytes = 0;
     int device = -1;
 };
+
+
+namespace {
+
+// Fans per table of a plan.  The step runs as two chains of launches on two
+// streams, half the fans each, so that one chain's kernels fill the other's
+// tails; not for the deterministic plan (one chain), nor when some ray is
+// long enough for several wavefronts (its launches take the second stream),
+// nor for a single fan.
+int plan_max_fans(const dus_plan *p)
+{
+    int nonempty = 0;
+    bool long_rays = false;
+    for (const auto &f : p->fans) {
+        if (f.n_rays <= 0 || f.n_samples <= 0) continue;
+        ++nonempty;
+        long_rays = long_rays || (p->sched.span_samples > 0 && f.n_samples >= p->sched.span_samples);
+    }
+    if (nonempty < 2 || long_rays || (p->flags & DUS_PLAN_DETERMINISTIC)) return dus::kMaxFans;
+    return std::min(dus::kMaxFans, (nonempty + 1) / 2);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -720,7 +752,8 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, 
     p->fans.assign(fans, fans + n_poses);
     p->phys = *phys;
     p->flags = flags;
-    p->tabs = build_tables(fans, n_poses);
+    p->max_fans = plan_max_fans(p);
+    p->tabs = build_tables(fans, n_poses, p->max_fans);
     p->ws = layout(fans, n_poses, phys, 2, (flags & DUS_PLAN_POSE_ONLY) != 0,
                    (flags & DUS_PLAN_DETERMINISTIC) ? (int64_t)vol->nx * vol->ny * vol->nz : 0);
     p->extent = image_extent(fans, n_poses);
@@ -729,6 +762,7 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, 
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side.st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->side.fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->side.join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->cleared, hipEventDisableTiming);
     if (e != hipSuccess) {
         dus_plan_destroy(p);
         return hip_fail(e, "plan streams and events");
@@ -759,6 +793,11 @@ int dus_plan_set_schedule(dus_plan *p, const dus_schedule *sc)
     if ((s = make_sched(sc, n)) != DUS_OK) return s;
     p->sched = n;
     plan_drop_graph(p);
+    const int mf = plan_max_fans(p);
+    if (mf != p->max_fans) {
+        p->max_fans = mf;
+        p->tabs = build_tables(p->fans.data(), (int32_t)p->fans.size(), mf);
+    }
     return DUS_OK;
 }
 
@@ -838,15 +877,35 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     zero.b = acc;
     zero.nb = grad_pose ? (int64_t)n_poses * dus::kPoseAcc : 0;
     const bool fwd_clears = fwd && p->extent > 0;
+    // two chains: the tables alternate between the step's stream and the
+    // plan's second stream (forked after the clears, joined before the end).
+    // One chain for the phase-timed step, for the deterministic plan (its
+    // scale needs every table's dL/dZ before any scatter), and when some ray
+    // is long (plan_max_fans; the second stream then takes the long rays'
+    // launches: a third stream forked from the second one crashed the host
+    // process in graph capture)
+    const bool two = (ev == nullptr) && p->tabs.size() >= 2 && !fix && p->max_fans < dus::kMaxFans;
+    auto tst = [&](size_t i) { return (two && (i % 2)) ? p->side.st : st; };
+    const dus::SideStream *side = two ? nullptr : &p->side;
     DUS_HIP(mark(DUS_PHASE_CLEAR), "event");
     if (!fwd_clears) DUS_HIP(dus::launch_zero_pair(zero.a, zero.na, zero.b, zero.nb, st), "zero kernel");
+    if (two) {
+        DUS_HIP(hipEventRecord(p->side.fork, st), "fork event");
+        DUS_HIP(hipStreamWaitEvent(p->side.st, p->side.fork, 0), "fork wait");
+    }
     DUS_HIP(mark(DUS_PHASE_FORWARD), "event");
     if (fwd) {
-        int s;
         float *img = blur ? reinterpret_cast<float *>((char *)ws + p->ws.pre) : bmode;
-        if ((s = enqueue_forward(sc, va, pa, p->tabs, poses, img, nullptr, st, car, cex, cst, gain,
-                                 fwd_clears ? zero : dus::ZeroArgs{}, &p->side)) != DUS_OK)
-            return s;
+        for (size_t i = 0; i < p->tabs.size(); ++i) {
+            const auto &t = p->tabs[i];
+            if (t.total_rays <= 0) continue;
+            // the first table's forward clears dL/dZ and the pose sums
+            DUS_HIP(dus::launch_forward(sc.fwd_chunk, sc.xcd_group, va, pa, t, poses, img, nullptr, 0, car, cex, cst,
+                                        gain, tst(i), (i == 0 && fwd_clears) ? zero : dus::ZeroArgs{},
+                                        sc.span_samples, side),
+                    "forward kernel launch");
+            if (i == 0 && two && fwd_clears) DUS_HIP(hipEventRecord(p->cleared, st), "clear event");
+        }
     }
     DUS_HIP(mark(DUS_PHASE_BLUR_LOSS), "event");
     const float *eb = nullptr;
@@ -854,8 +913,10 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         const float *pre = reinterpret_cast<float *>((char *)ws + p->ws.pre);
         float *res = p->ws.res_bytes ? reinterpret_cast<float *>((char *)ws + p->ws.res) : nullptr;
         float *ebw = reinterpret_cast<float *>((char *)ws + p->ws.eb);
-        for (const auto &t : p->tabs) {
-            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, ebw, loss ? part + n_part : nullptr, st),
+        for (size_t i = 0; i < p->tabs.size(); ++i) {
+            const auto &t = p->tabs[i];
+            DUS_HIP(dus::launch_blur_residual(pa, t, pre, target, bmode, res, ebw, loss ? part + n_part : nullptr,
+                                              tst(i)),
                     "blur/loss kernel");
             n_part += t.total_blur_blocks;
         }
@@ -867,7 +928,8 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     const bool adj = blur ? (gZ || grad_pose) : true;
     int64_t r0 = 0;        // rays of the tables before this one (pose partials)
     if (adj)
-        for (const auto &t : p->tabs) {
+        for (size_t i = 0; i < p->tabs.size(); ++i) {
+            const auto &t = p->tabs[i];
             // dL/dZ per sample is stored only for the scatter
             DUS_HIP(dus::launch_adjoint(sc.bwd_chunk, sc.xcd_group, va, pa, t, poses, gZ ? rays + r0 : nullptr, eb,
                                         blur ? nullptr : target,
@@ -875,11 +937,14 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
                                         grad_pose ? acc : nullptr, rpart + dus::kRayPart * r0,
                                         (!blur && loss) ? part + n_part : nullptr,
                                         fwd ? car : nullptr, fwd ? cex : nullptr, fwd ? cst : nullptr,
-                                        fwd ? gain : nullptr, st, sc.span_samples, &p->side),
+                                        fwd ? gain : nullptr, tst(i), sc.span_samples, side),
                     "adjoint kernel");
             if (!blur) n_part += t.total_rays;
             r0 += t.total_rays;
         }
+    // the second chain's scatters and pose sums wait for the first table's
+    // forward, which clears what they add to
+    if (two && fwd_clears) DUS_HIP(hipStreamWaitEvent(p->side.st, p->cleared, 0), "clear wait");
     DUS_HIP(mark(DUS_PHASE_SCATTER), "event");
     if (adj && gZ) {
         if (fix) {
@@ -891,8 +956,9 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
             DUS_HIP(dus::launch_fix_scale(fsc + 4, r0, fsc, st), "fixed-point scale kernel");
         }
         r0 = 0;
-        for (const auto &t : p->tabs) {
-            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, rays + r0, zbar, gZ, st, fix, fsc),
+        for (size_t i = 0; i < p->tabs.size(); ++i) {
+            const auto &t = p->tabs[i];
+            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, rays + r0, zbar, gZ, tst(i), fix, fsc),
                     "scatter kernel");
             r0 += t.total_rays;
         }
@@ -903,10 +969,15 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     DUS_HIP(mark(DUS_PHASE_FINISH), "event");
     if (adj && grad_pose) {
         r0 = 0;
-        for (const auto &t : p->tabs) {
-            DUS_HIP(dus::launch_pose_reduce(t, rpart + dus::kRayPart * r0, acc, st), "pose reduction kernel");
+        for (size_t i = 0; i < p->tabs.size(); ++i) {
+            const auto &t = p->tabs[i];
+            DUS_HIP(dus::launch_pose_reduce(t, rpart + dus::kRayPart * r0, acc, tst(i)), "pose reduction kernel");
             r0 += t.total_rays;
         }
+    }
+    if (two) {
+        DUS_HIP(hipEventRecord(p->side.join, p->side.st), "join event");
+        DUS_HIP(hipStreamWaitEvent(st, p->side.join, 0), "join wait");
     }
     DUS_HIP(dus::launch_finish(part, n_part, loss, acc, poses, n_poses, grad_pose, st), "loss and pose kernel");
     DUS_HIP(mark(DUS_NUM_PHASES), "event");
@@ -987,6 +1058,7 @@ void dus_plan_destroy(dus_plan *p)
     if (p->side.st) (void)hipStreamDestroy(p->side.st);
     if (p->side.fork) (void)hipEventDestroy(p->side.fork);
     if (p->side.join) (void)hipEventDestroy(p->side.join);
+    if (p->cleared) (void)hipEventDestroy(p->cleared);
     delete p;
 }
 
