@@ -240,13 +240,17 @@ def skewed_batch(Z, dev, reps: int, ev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    # the GPU's clock climbs over the first tens of milliseconds of steady
+    # work: about 100 steps (60 ms) of warm-up before the timed steps
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--poses", type=int, default=64)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="profiling runs: the timed step too on one stream (one launch per kernel and step)")
     ap.add_argument("--step-only", action="store_true",
                     help="skip the uneven and skewed batches (profiling runs: every launch at the step's "
                          "grid then belongs to the step)")
@@ -276,7 +280,7 @@ def main():
     N = geom.total
     log("bench: targets rendered")
 
-    step = FusedStep(geom, zero_grad_z=True)
+    step = FusedStep(geom, zero_grad_z=True, one_stream=args.one_stream)
     gZ = torch.zeros_like(Z)
     gp = torch.empty((B, 6), device=dev)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -337,23 +341,32 @@ def main():
         plain_ms = timed(plain, max(2, args.steps // 4), ev)
         log(f"bench: plain per-pose step {plain_ms:.3f} ms")
 
-    # per-kernel durations inside the step: the same plan launched eagerly
-    # with HIP events at the phase boundaries (on the launch stream).  Each
-    # timed step is queued right behind a graph-replayed one, so the GPU is
-    # busy when it starts, as in the timed region, rather than idle after a
-    # host wait.
+    # per-kernel durations: the step splits the fans into two chains of
+    # launches on two streams, whose kernels overlap, so the kernels are
+    # timed on the same workload in a plan held to one stream (one launch
+    # per kernel over all 16384 rays), launched eagerly with HIP events at
+    # the phase boundaries (on the launch stream).  Each timed step is queued
+    # right behind a graph replay of that plan, so the GPU is busy when it
+    # starts, as in the timed region, rather than idle after a host wait.
+    step1 = FusedStep(geom, zero_grad_z=True, one_stream=True)
+    step1.set_schedule(**step.get_schedule())
+    fused1 = lambda: step1.step(Z, poses, target, loss=loss, grad_Z=gZ, grad_pose=gp)  # noqa: E731
+    for _ in range(args.warmup):
+        fused1()
+    ms_one = timed(fused1, args.steps, ev)
+    log(f"bench: fused batched step on one stream {ms_one:.3f} ms")
     reps = max(5, args.steps // 2)
     phases = None
     for _ in range(reps):
-        fused()
-        ph_ms = step.step_timed(Z, poses, target, loss=loss, grad_Z=gZ, grad_pose=gp)
+        fused1()
+        ph_ms = step1.step_timed(Z, poses, target, loss=loss, grad_Z=gZ, grad_pose=gp)
         phases = ph_ms if phases is None else {k: phases[k] + v for k, v in ph_ms.items()}
     phases = {k: v / reps for k, v in phases.items()}
     log(f"bench: phases (ms) {json.dumps(phases)}")
     # the eager step pays a launch gap at every phase boundary that the graph
     # replay does not: each phase's kernel time is its eager time scaled by
-    # (graph-replayed step / sum of the eager phases)
-    gap_scale = ms / sum(phases.values())
+    # (graph-replayed one-stream step / sum of the eager phases)
+    gap_scale = ms_one / sum(phases.values())
     vfp = footprint_voxels(poses, geom)
     n_vox = int(np.prod(case.Z.shape))
     # algorithmic bytes per launch (per ray-sample figures times N, per
@@ -448,6 +461,7 @@ def main():
         "modes": modes,
         "phases_ms": phases,
         "phase_gap_scale": gap_scale,
+        "ms_per_step_one_stream": ms_one,
         "kernels": kern,
         "roofline": {
             "bound": bound,

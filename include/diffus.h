@@ -308,10 +308,14 @@ enum {
     DUS_PLAN_POSE_ONLY = 1,   /* grad_Z is neither needed nor touched */
     DUS_PLAN_ZERO_GRAD_Z = 2, /* the step clears grad_Z itself (fill kernel) */
     DUS_PLAN_NO_GRAPH = 4,    /* launch eagerly instead of replaying a graph */
-    DUS_PLAN_DETERMINISTIC = 8 /* dL/dZ bit-identical from step to step: summed as 64-bit fixed
-                                  point (scale 2^e set per step from the sum of |dL/dZ| over all
-                                  samples, so no sum can overflow) and rounded once to FP32,
-                                  instead of FP32 atomics; costs 8 B per voxel of workspace */
+    DUS_PLAN_DETERMINISTIC = 8, /* dL/dZ bit-identical from step to step: summed as 64-bit fixed
+                                   point (scale 2^e set per step from the sum of |dL/dZ| over all
+                                   samples, so no sum can overflow) and rounded once to FP32,
+                                   instead of FP32 atomics; costs 8 B per voxel of workspace */
+    DUS_PLAN_ONE_STREAM = 16   /* every launch on the step's stream, the fans in tables of up to 64
+                                  (by default a plan of two or more fans runs them as two chains of
+                                  launches, half the fans each, on the step's stream and a second
+                                  one, and long rays' launches beside the others) */
 };
 
 /* Ray-to-wavefront schedule; 0 fields select the library default. */

@@ -18,7 +18,7 @@ c_i32, c_i64, c_f32, c_u64, c_sz, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes
 DUS_OK, DUS_EINVAL, DUS_ESHAPE, DUS_EWORKSPACE, DUS_EHIP, DUS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 REFL_ABS, REFL_SIGNED = 0, 1
 ATTEN_IN_SYSTEM, ATTEN_POST_HOC, ATTEN_OFF = 0, 1, 2
-PLAN_POSE_ONLY, PLAN_ZERO_GRAD_Z, PLAN_NO_GRAPH, PLAN_DETERMINISTIC = 1, 2, 4, 8
+PLAN_POSE_ONLY, PLAN_ZERO_GRAD_Z, PLAN_NO_GRAPH, PLAN_DETERMINISTIC, PLAN_ONE_STREAM = 1, 2, 4, 8, 16
 # phases of a plan step (DUS_PHASE_*), in launch order
 PHASES = ("clear", "forward", "blur_loss", "adjoint", "scatter", "finish")
 MAX_SAMPLES, MAX_RAYS, MAX_BLUR_RADIUS = 16384, 65536, 32

@@ -421,9 +421,9 @@ namespace {
 
 // Fans per table of a plan.  The step runs as two chains of launches on two
 // streams, half the fans each, so that one chain's kernels fill the other's
-// tails; not for the deterministic plan (one chain), nor when some ray is
-// long enough for several wavefronts (its launches take the second stream),
-// nor for a single fan.
+// tails; not for the deterministic plan (one chain), nor for a plan held to
+// one stream, nor when some ray is long enough for several wavefronts (its
+// launches take the second stream), nor for a single fan.
 int plan_max_fans(const dus_plan *p)
 {
     int nonempty = 0;
@@ -433,7 +433,7 @@ int plan_max_fans(const dus_plan *p)
         ++nonempty;
         long_rays = long_rays || (p->sched.span_samples > 0 && f.n_samples >= p->sched.span_samples);
     }
-    if (nonempty < 2 || long_rays || (p->flags & DUS_PLAN_DETERMINISTIC)) return dus::kMaxFans;
+    if (nonempty < 2 || long_rays || (p->flags & (DUS_PLAN_DETERMINISTIC | DUS_PLAN_ONE_STREAM))) return dus::kMaxFans;
     return std::min(dus::kMaxFans, (nonempty + 1) / 2);
 }
 
@@ -744,7 +744,8 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, 
     if ((s = check_volume(vol)) != DUS_OK) return s;
     if ((s = check_physics(phys)) != DUS_OK) return s;
     if ((s = check_fans(fans, n_poses)) != DUS_OK) return s;
-    if (flags & ~(DUS_PLAN_POSE_ONLY | DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH | DUS_PLAN_DETERMINISTIC))
+    if (flags & ~(DUS_PLAN_POSE_ONLY | DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH | DUS_PLAN_DETERMINISTIC |
+                  DUS_PLAN_ONE_STREAM))
         return fail(DUS_EINVAL, "unknown plan flag");
     dus_plan *p = new (std::nothrow) dus_plan();
     if (!p) return fail(DUS_EINVAL, "out of host memory");
@@ -886,7 +887,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     // process in graph capture)
     const bool two = (ev == nullptr) && p->tabs.size() >= 2 && !fix && p->max_fans < dus::kMaxFans;
     auto tst = [&](size_t i) { return (two && (i % 2)) ? p->side.st : st; };
-    const dus::SideStream *side = two ? nullptr : &p->side;
+    const dus::SideStream *side = (two || (p->flags & DUS_PLAN_ONE_STREAM)) ? nullptr : &p->side;
     DUS_HIP(mark(DUS_PHASE_CLEAR), "event");
     if (!fwd_clears) DUS_HIP(dus::launch_zero_pair(zero.a, zero.na, zero.b, zero.nb, st), "zero kernel");
     if (two) {

@@ -353,15 +353,20 @@ def footprint_voxels(poses: torch.Tensor, geom: Geometry) -> int:
 
 class FusedStep:
     """Batched fused forward + MSE + adjoint over all poses of ``geom``,
-    replayed from a captured HIP graph (``dus_plan``)."""
+    replayed from a captured HIP graph (``dus_plan``).  ``deterministic``:
+    dL/dZ bit-identical from step to step; ``one_stream``: every launch on
+    the caller's stream (by default the fans run as two chains of launches
+    on two streams)."""
 
     def __init__(self, geom: Geometry, pose_only: bool = False, zero_grad_z: bool = True,
-                 graph: bool = True, schedule: dict | None = None, deterministic: bool = False):
+                 graph: bool = True, schedule: dict | None = None, deterministic: bool = False,
+                 one_stream: bool = False):
         L = _lib.lib()
         self.geom = geom
         flags = (_lib.PLAN_POSE_ONLY if pose_only else 0) | (_lib.PLAN_ZERO_GRAD_Z if zero_grad_z else 0)
         flags |= 0 if graph else _lib.PLAN_NO_GRAPH
         flags |= _lib.PLAN_DETERMINISTIC if deterministic else 0
+        flags |= _lib.PLAN_ONE_STREAM if one_stream else 0
         h = ctypes.c_void_p()
         check(L.dus_plan_create(ctypes.byref(h), ctypes.byref(geom.vol_c), geom.fans_c, geom.n_poses,
                                 ctypes.byref(geom.phys_c), flags), "dus_plan_create")

@@ -115,7 +115,8 @@ int main()
                        "backward, static scratch");
                 for (int flags : {0, (int)DUS_PLAN_POSE_ONLY, (int)DUS_PLAN_ZERO_GRAD_Z, (int)DUS_PLAN_NO_GRAPH,
                                   (int)(DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH), (int)DUS_PLAN_DETERMINISTIC,
-                                  (int)(DUS_PLAN_DETERMINISTIC | DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH)}) {
+                                  (int)(DUS_PLAN_DETERMINISTIC | DUS_PLAN_ZERO_GRAD_Z | DUS_PLAN_NO_GRAPH),
+                                  (int)DUS_PLAN_ONE_STREAM, (int)(DUS_PLAN_ONE_STREAM | DUS_PLAN_NO_GRAPH)}) {
                     dus_plan *plan = nullptr;
                     expect(dus_plan_create(&plan, &v, f.data(), nf, &p, flags) == DUS_OK, "plan create");
                     const int64_t wsp = dus_plan_workspace_bytes(plan);

@@ -328,9 +328,16 @@ def test_graph_replays_agree():
     eager.step(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
     torch.cuda.synchronize()
     ref = (bm.cpu().numpy(), loss.item(), gZ.cpu().numpy(), gp.cpu().numpy())
-    # the phase-timed step launches the same kernels eagerly
+    # the phase-timed step launches the same kernels eagerly, on one stream
     ms = eager.step_timed(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
     res.append((bm.cpu().numpy().copy(), loss.item(), gZ.cpu().numpy().copy(), gp.cpu().numpy().copy()))
+    # a plan held to one stream (one table, one chain of launches)
+    one = FusedStep(geom, zero_grad_z=True, one_stream=True)
+    for _ in range(2):
+        one.step(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+    torch.cuda.synchronize()
+    res.append((bm.cpu().numpy().copy(), loss.item(), gZ.cpu().numpy().copy(), gp.cpu().numpy().copy()))
+    one.close()
     assert all(v >= 0.0 for v in ms.values()) and ms["forward"] > 0 and ms["adjoint"] > 0 and ms["scatter"] > 0
     for r in res:
         np.testing.assert_array_equal(r[0], ref[0])
