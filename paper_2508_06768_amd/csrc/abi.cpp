@@ -165,17 +165,45 @@ dus::PhysArgs phys_args(const dus_physics *p)
 
 // Fan tables of at most kMaxFans fans, each sorted longest ray first so the
 // hardware dispatcher starts the longest rays first.
-std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses, int max_fans = dus::kMaxFans)
+// Launch tables of at most kMaxFans fans each.  two_groups (a plan's two
+// chains of launches): the fans are first split into two groups of about
+// equal ray-samples (each fan, largest first, to the lighter group), and
+// the groups' tables alternate, so that tables 0, 2, ... hold the first
+// group and 1, 3, ... the second.
+std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses, bool two_groups = false)
 {
     std::vector<int> pivot_begin(n_poses + 1, 0);
     for (int i = 0; i < n_poses; ++i) pivot_begin[i + 1] = pivot_begin[i] + std::max(0, fans[i].n_rays);
     std::vector<int> order;
     for (int i = 0; i < n_poses; ++i)
         if (fans[i].n_rays > 0 && fans[i].n_samples > 0) order.push_back(i);
+    std::vector<std::vector<int>> grps;
+    if (!two_groups) {
+        for (size_t g0 = 0; g0 < order.size(); g0 += (size_t)dus::kMaxFans)
+            grps.emplace_back(order.begin() + g0, order.begin() + std::min(order.size(), g0 + (size_t)dus::kMaxFans));
+    } else {
+        auto work = [&](int i) { return (int64_t)fans[i].n_rays * fans[i].n_samples; };
+        std::vector<int> by_work = order;
+        std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int b) { return work(a) > work(b); });
+        std::vector<int> half[2];
+        int64_t load[2] = {0, 0};
+        for (int i : by_work) {
+            const int h = (load[1] < load[0]) ? 1 : 0;
+            half[h].push_back(i);
+            load[h] += work(i);
+        }
+        std::vector<std::vector<int>> tabs_of[2];
+        for (int h = 0; h < 2; ++h)
+            for (size_t g0 = 0; g0 < half[h].size(); g0 += (size_t)dus::kMaxFans)
+                tabs_of[h].emplace_back(half[h].begin() + g0,
+                                        half[h].begin() + std::min(half[h].size(), g0 + (size_t)dus::kMaxFans));
+        for (size_t k = 0; k < std::max(tabs_of[0].size(), tabs_of[1].size()); ++k)
+            for (int h = 0; h < 2; ++h)
+                if (k < tabs_of[h].size()) grps.push_back(tabs_of[h][k]);
+    }
     std::vector<dus::FanTable> out;
     int64_t carries = 0;    // tile-carry records of all tables before this fan
-    for (size_t g0 = 0; g0 < order.size(); g0 += (size_t)max_fans) {
-        std::vector<int> grp(order.begin() + g0, order.begin() + std::min(order.size(), g0 + (size_t)max_fans));
+    for (auto &grp : grps) {
         std::stable_sort(grp.begin(), grp.end(),
                          [&](int a, int b) { return fans[a].n_samples > fans[b].n_samples; });
         dus::FanTable t;
@@ -408,7 +436,7 @@ struct dus_plan {
     // long, the launches of the long rays beside the one-wavefront ones
     dus::SideStream side{};
     hipEvent_t cleared = nullptr;   // the first table's forward has cleared dL/dZ and the pose sums
-    int max_fans = dus::kMaxFans;   // fans per table (two chains: half the fans each)
+    bool two_chains = false;        // the tables alternate between two chains of launches
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     const void *key[9] = {};
@@ -419,12 +447,13 @@ struct dus_plan {
 
 namespace {
 
-// Fans per table of a plan.  The step runs as two chains of launches on two
-// streams, half the fans each, so that one chain's kernels fill the other's
-// tails; not for the deterministic plan (one chain), nor for a plan held to
-// one stream, nor when some ray is long enough for several wavefronts (its
-// launches take the second stream), nor for a single fan.
-int plan_max_fans(const dus_plan *p)
+// Whether a plan's step runs as two chains of launches on two streams, the
+// fans split in two groups of about equal work, so that one chain's kernels
+// fill the other's tails: not for the deterministic plan (one chain), nor
+// for a plan held to one stream, nor when some ray is long enough for
+// several wavefronts (its launches take the second stream), nor for a
+// single fan.
+bool plan_two_chains(const dus_plan *p)
 {
     int nonempty = 0;
     bool long_rays = false;
@@ -433,8 +462,7 @@ int plan_max_fans(const dus_plan *p)
         ++nonempty;
         long_rays = long_rays || (p->sched.span_samples > 0 && f.n_samples >= p->sched.span_samples);
     }
-    if (nonempty < 2 || long_rays || (p->flags & (DUS_PLAN_DETERMINISTIC | DUS_PLAN_ONE_STREAM))) return dus::kMaxFans;
-    return std::min(dus::kMaxFans, (nonempty + 1) / 2);
+    return !(nonempty < 2 || long_rays || (p->flags & (DUS_PLAN_DETERMINISTIC | DUS_PLAN_ONE_STREAM)));
 }
 
 }  // namespace
@@ -753,8 +781,8 @@ int dus_plan_create(dus_plan **out, const dus_volume *vol, const dus_fan *fans, 
     p->fans.assign(fans, fans + n_poses);
     p->phys = *phys;
     p->flags = flags;
-    p->max_fans = plan_max_fans(p);
-    p->tabs = build_tables(fans, n_poses, p->max_fans);
+    p->two_chains = plan_two_chains(p);
+    p->tabs = build_tables(fans, n_poses, p->two_chains);
     p->ws = layout(fans, n_poses, phys, 2, (flags & DUS_PLAN_POSE_ONLY) != 0,
                    (flags & DUS_PLAN_DETERMINISTIC) ? (int64_t)vol->nx * vol->ny * vol->nz : 0);
     p->extent = image_extent(fans, n_poses);
@@ -794,10 +822,10 @@ int dus_plan_set_schedule(dus_plan *p, const dus_schedule *sc)
     if ((s = make_sched(sc, n)) != DUS_OK) return s;
     p->sched = n;
     plan_drop_graph(p);
-    const int mf = plan_max_fans(p);
-    if (mf != p->max_fans) {
-        p->max_fans = mf;
-        p->tabs = build_tables(p->fans.data(), (int32_t)p->fans.size(), mf);
+    const bool two = plan_two_chains(p);
+    if (two != p->two_chains) {
+        p->two_chains = two;
+        p->tabs = build_tables(p->fans.data(), (int32_t)p->fans.size(), two);
     }
     return DUS_OK;
 }
@@ -882,10 +910,10 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     // plan's second stream (forked after the clears, joined before the end).
     // One chain for the phase-timed step, for the deterministic plan (its
     // scale needs every table's dL/dZ before any scatter), and when some ray
-    // is long (plan_max_fans; the second stream then takes the long rays'
+    // is long (plan_two_chains; the second stream then takes the long rays'
     // launches: a third stream forked from the second one crashed the host
     // process in graph capture)
-    const bool two = (ev == nullptr) && p->tabs.size() >= 2 && !fix && p->max_fans < dus::kMaxFans;
+    const bool two = (ev == nullptr) && p->tabs.size() >= 2 && !fix && p->two_chains;
     auto tst = [&](size_t i) { return (two && (i % 2)) ? p->side.st : st; };
     const dus::SideStream *side = (two || (p->flags & DUS_PLAN_ONE_STREAM)) ? nullptr : &p->side;
     DUS_HIP(mark(DUS_PHASE_CLEAR), "event");
