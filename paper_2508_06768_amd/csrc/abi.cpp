@@ -987,7 +987,9 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
         r0 = 0;
         for (size_t i = 0; i < p->tabs.size(); ++i) {
             const auto &t = p->tabs[i];
-            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, rays + r0, zbar, gZ, tst(i), fix, fsc),
+            // two chains: two scatters at a time share the wavefront budget
+            DUS_HIP(dus::launch_scatter(sc.scatter_rays, sc.xcd_group, va, t, rays + r0, zbar, gZ, tst(i), fix, fsc,
+                                        two ? 16384 : 32768),
                     "scatter kernel");
             r0 += t.total_rays;
         }

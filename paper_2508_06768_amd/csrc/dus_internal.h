@@ -144,10 +144,13 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
 // per fan (fixed order)
 hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double *pose_acc, hipStream_t st);
 // fix (nullable): deterministic mode, 64-bit fixed-point sums at the scale
-// fscale[0] (launch_fix_scale) instead of FP32 atomics into gZ
+// fscale[0] (launch_fix_scale) instead of FP32 atomics into gZ; wave_target:
+// about how many wavefronts the depth segments should make (that of the
+// launches running at the same time)
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
                           const RayRec *rays, const float *zbar, float *gZ, hipStream_t st,
-                          unsigned long long *fix = nullptr, const double *fscale = nullptr);
+                          unsigned long long *fix = nullptr, const double *fscale = nullptr,
+                          int wave_target = 32768);
 // deterministic dL/dZ: part[r] = the sum of |zbar| along the table's ray r
 // (one double per ray); fscale[2] = the sum of part[0..n), fscale[0..1] =
 // 2^e and 2^-e from it; the conversion of the fixed-point sums into gZ

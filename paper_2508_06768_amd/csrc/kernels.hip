@@ -2671,16 +2671,17 @@ hipError_t launch_pose_reduce(const FanTable &t, const double *pose_part, double
 
 hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, const FanTable &t,
                           const RayRec *rays, const float *zbar, float *gZ, hipStream_t st,
-                          unsigned long long *fix, const double *fscale)
+                          unsigned long long *fix, const double *fscale, int wave_target)
 {
     if (t.total_rays <= 0 || (!gZ && !fix)) return hipSuccess;
     if (!zbar || !rays || (fix && !fscale)) return hipErrorInvalidValue;
     // depth segments, the same power-of-two length for every fan, a whole
     // number of the largest groups (256 / RB depths): the shortest that
-    // keeps the launch within about 32 wavefronts per SIMD (a wavefront's
-    // set-up is a few loads, so short segments cost little and even out the
-    // finishing times; a fan of long rays gets as many wavefronts per ray as
-    // its length asks for)
+    // keeps the launch within wave_target wavefronts, about 32 per SIMD over
+    // the launches that run at the same time (a wavefront's set-up is a few
+    // loads, so short segments cost little and even out the finishing times;
+    // a fan of long rays gets as many wavefronts per ray as its length asks
+    // for)
     auto units = [&](int rb, int sg) {
         long long u = 0;
         for (int f = 0; f < t.n; ++f)
@@ -2691,7 +2692,7 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
     // segments leave fewer than two wavefronts per SIMD; then two
     if (scatter_rays == 0) scatter_rays = (units(8, 32) < 2048) ? 2 : 8;
     int seg = 256 / scatter_rays, seg_shift = 0;
-    while (seg < DUS_MAX_SAMPLES && units(scatter_rays, seg) > 32768) seg *= 2;
+    while (seg < DUS_MAX_SAMPLES && units(scatter_rays, seg) > std::max(wave_target, 1024)) seg *= 2;
     while ((1 << seg_shift) < seg) ++seg_shift;
     const long long nunits = units(scatter_rays, seg);
     if (nunits <= 0) return hipSuccess;

@@ -162,7 +162,7 @@ hipError_t launch_pose_reduce(const FanTable &t, const double *, double *, hipSt
     return hipSuccess;
 }
 hipError_t launch_scatter(int, int, const VolArgs &, const FanTable &t, const RayRec *, const float *, float *,
-                          hipStream_t, unsigned long long *, const double *)
+                          hipStream_t, unsigned long long *, const double *, int)
 {
     check_table(t);
     return hipSuccess;
