@@ -365,8 +365,13 @@ int dus_plan_get_schedule(const dus_plan *plan, dus_schedule *sched);
  * One fused step of the plan (Sec. 2.3-2.4 forward, MSE, adjoint; see above)
  * on `stream`: the first call, and any call whose pointers or workspace size
  * differ from the previous call's, captures a new HIP graph; the others
- * replay it.  Z and poses as for dus_render_bmode; the workspace has at
- * least dus_plan_workspace_bytes(plan) bytes, 256-byte aligned.
+ * replay it.  Unless the plan was created with DUS_PLAN_ONE_STREAM, the step
+ * also runs launches on the plan's second stream (two chains of launches,
+ * or the long rays' launches), forked from `stream` and joined back into it
+ * before the step's last launch, so the step is ordered on `stream` all the
+ * same; two steps of one plan must not run at the same time.  Z and poses
+ * as for dus_render_bmode; the workspace has at least
+ * dus_plan_workspace_bytes(plan) bytes, 256-byte aligned.
  *   target   device FP32, same layout as bmode
  *   bmode    device FP32 or NULL: the rendered image is also written
  *   loss     device FP64 scalar or NULL: receives the loss (overwritten)
@@ -399,8 +404,9 @@ enum {
 };
 
 /*
- * dus_plan_step without graph replay, with a HIP event recorded on `stream`
- * at every phase boundary.  Same arguments and results as dus_plan_step;
+ * dus_plan_step without graph replay and on `stream` alone (one chain of
+ * launches), with a HIP event recorded on `stream` at every phase boundary.
+ * Same arguments and results as dus_plan_step;
  * ms[DUS_PHASE_*] receives each phase's duration in milliseconds (0 for a
  * phase the step does not run).  Blocks the calling thread until the step
  * has finished on the device.  Creates and destroys its events (no device

@@ -60,11 +60,11 @@ def test_long_rays_match_oracle(refl, effects):
         _check_plan(case, _run_plan(case, target, sched, replays=2), ref, f"long rays fwd {fc} bwd {bc}")
 
 
-def _det_step(case, target, span, fc=8, bc=4):
+def _det_step(case, target, span, fc=8, bc=4, one_stream=False):
     from paper_2508_06768_amd.render import FusedStep
     geom, Z, P = _gpu(case)
     T = torch.from_numpy(target.astype(np.float32)).to(DEV)
-    step = FusedStep(geom, zero_grad_z=True, deterministic=True,
+    step = FusedStep(geom, zero_grad_z=True, deterministic=True, one_stream=one_stream,
                      schedule={"fwd_chunk": fc, "bwd_chunk": bc, "span_samples": span})
     bm = torch.empty(geom.total, device=DEV)
     gZ = torch.empty_like(Z)
@@ -93,6 +93,20 @@ def test_spans_bit_identical(which, fc, bc):
     np.testing.assert_allclose(a[3], b[3], rtol=1e-10, atol=1e-12 * np.abs(b[3]).max())
     img, ref_loss, rV, rp = _plan_reference(case, target)
     _check_plan(case, (a[0], a[1], a[2], a[3]), (img, ref_loss, rV, rp), f"spans {which}")
+
+
+def test_spans_on_one_stream():
+    """A plan held to one stream launches the long rays' wavefronts on the
+    step's stream, after the others: the same images and dL/dZ bit for bit
+    as the default plan, whose second stream takes them."""
+    case = long_column_case(1, True, seed=39)
+    target = H.oracle_render(case, poses=case.poses + np.float32([[-0.2, 0.1, 0.2, 0.0, 0.01, 0.0]]))
+    a = _det_step(case, target, 0)
+    b = _det_step(case, target, 0, one_stream=True)
+    np.testing.assert_array_equal(a[0], b[0])
+    assert a[1] == b[1]
+    np.testing.assert_array_equal(a[2], b[2])
+    np.testing.assert_array_equal(a[3], b[3])
 
 
 def test_spans_forward_render_bit_identical():
