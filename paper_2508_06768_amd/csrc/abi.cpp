@@ -915,7 +915,10 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     // process in graph capture)
     const bool two = (ev == nullptr) && p->tabs.size() >= 2 && !fix && p->two_chains;
     auto tst = [&](size_t i) { return (two && (i % 2)) ? p->side.st : st; };
-    const dus::SideStream *side = (two || (p->flags & DUS_PLAN_ONE_STREAM)) ? nullptr : &p->side;
+    // the long rays' launches take the second stream unless the step keeps
+    // to one stream (one-stream plan, phase-timed step) or it carries the
+    // second chain
+    const dus::SideStream *side = (two || ev || (p->flags & DUS_PLAN_ONE_STREAM)) ? nullptr : &p->side;
     DUS_HIP(mark(DUS_PHASE_CLEAR), "event");
     if (!fwd_clears) DUS_HIP(dus::launch_zero_pair(zero.a, zero.na, zero.b, zero.nb, st), "zero kernel");
     if (two) {
