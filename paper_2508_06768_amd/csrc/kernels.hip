@@ -221,7 +221,8 @@ __device__ __forceinline__ void axis_cell(double u, int n, int &i0, double &f)
     const double uc = INSIDE ? u : fmin(fmax(u, 0.0), (double)(n - 1));
     const int i = INSIDE ? (int)uc : min((int)uc, n - 2);
     i0 = i;
-    f = uc - (double)i;
+    // inside, u - floor(u) is exact and one instruction
+    f = INSIDE ? __builtin_amdgcn_fract(uc) : uc - (double)i;
 }
 
 struct Stencil {
