@@ -186,7 +186,13 @@ std::vector<dus::FanTable> build_tables(const dus_fan *fans, int32_t n_poses, bo
         std::vector<int> by_work = order;
         std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int b) { return work(a) > work(b); });
         std::vector<int> half[2];
-        int64_t load[2] = {0, 0};
+        // the first group (the step's own stream) starts one 64th of the
+        // work ahead: the second chain begins after the fork and is joined
+        // at the end, each about 10 us on the device (bench step and
+        // uneven batch 1% faster, equal fans of 316 samples 1% slower)
+        int64_t total = 0;
+        for (int i : by_work) total += work(i);
+        int64_t load[2] = {-total / 64, 0};
         for (int i : by_work) {
             const int h = (load[1] < load[0]) ? 1 : 0;
             half[h].push_back(i);
