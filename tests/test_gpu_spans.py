@@ -126,3 +126,38 @@ def test_spans_forward_render_bit_identical():
     np.testing.assert_array_equal(imgs[0], imgs[2])
     np.testing.assert_array_equal(imgs[1], imgs[2])
     _check_images(imgs[1], H.oracle_render(case), "render with spans", case.fans)
+
+
+def test_schedule_change_regroups_the_plan():
+    """A plan with long rays runs one chain (their launches take the second
+    stream); with span_samples = -1 it has no long rays and regroups its
+    fans into two chains, in the same workspace.  Images stay the same bit
+    for bit, the loss and the gradients within their rounding."""
+    from paper_2508_06768_amd import _lib
+    from paper_2508_06768_amd.render import FusedStep
+    case = long_column_case(0, True, seed=41)
+    geom, Z, P = _gpu(case)
+    target = H.oracle_render(case, poses=case.poses + np.float32([[0.1, 0.1, 0.1, 0.0, 0.0, 0.01]]))
+    T = torch.from_numpy(target.astype(np.float32)).to(DEV)
+    step = FusedStep(geom, zero_grad_z=True)
+    ws_bytes = _lib.lib().dus_plan_workspace_bytes(step._h)
+    out = []
+    for span in (0, -1, 0):
+        step.set_schedule(span_samples=span)
+        assert _lib.lib().dus_plan_workspace_bytes(step._h) == ws_bytes
+        bm = torch.empty(geom.total, device=DEV)
+        gZ = torch.empty_like(Z)
+        gp = torch.empty((geom.n_poses, 6), device=DEV)
+        loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+        for _ in range(2):
+            step.step(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+        torch.cuda.synchronize()
+        out.append((bm.cpu().numpy(), loss.item(), gZ.cpu().numpy().astype(np.float64), gp.cpu().numpy().astype(np.float64)))
+    step.close()
+    for o in out[1:]:
+        np.testing.assert_array_equal(o[0], out[0][0])
+        assert o[1] == pytest.approx(out[0][1], rel=1e-12)
+        assert H.rel_l2(o[2], out[0][2]) <= 1e-6
+        np.testing.assert_allclose(o[3], out[0][3], rtol=1e-9, atol=1e-12 * np.abs(out[0][3]).max())
+    img, ref_loss, rV, rp = _plan_reference(case, target)
+    _check_plan(case, out[1], (img, ref_loss, rV, rp), "regrouped plan")
