@@ -1,7 +1,8 @@
 """Schedule autotuner for the fused step.
 
 The kernels take a ray-to-wavefront schedule (``dus_schedule``): interfaces
-per lane per tile in the forward (4, 8, 16) and the adjoint (4, 8), the
+per lane per tile in the forward (0 = chosen per fan table, 4, 8, 16) and the
+adjoint (4, 8), the
 number of neighbouring rays that share one LDS box in the dL/dZ scatter (2,
 4, 8), the number of consecutive rays kept on one XCD (1..64), and the ray
 length from which several wavefronts share a ray (``span_samples``: never,
@@ -20,7 +21,7 @@ import os
 
 import torch
 
-FWD_CHUNKS = (4, 8, 16)
+FWD_CHUNKS = (0, 4, 8, 16)
 BWD_CHUNKS = (4, 8)
 XCD_GROUPS = (1, 4, 8, 16, 32, 64)
 SCATTER_RAYS = (2, 4, 8)

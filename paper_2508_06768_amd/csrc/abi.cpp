@@ -37,7 +37,7 @@ int hip_fail(hipError_t e, const char *where)
 
 bool finite_f(float x) { return isfinite(x) != 0; }
 
-constexpr int kDefaultFwdChunk = 8;
+constexpr int kDefaultFwdChunk = 0;       // automatic per fan table (launch_forward)
 constexpr int kDefaultBwdChunk = 4;
 constexpr int kDefaultXcdGroup = 16;
 constexpr int kDefaultScatterRays = 0;     // automatic (launch_scatter)
@@ -397,7 +397,8 @@ int make_sched(const dus_schedule *sc, Sched &n)
     n.scatter_rays = sc->scatter_rays ? sc->scatter_rays : kDefaultScatterRays;
     if (n.scatter_rays != 0 && n.scatter_rays != 2 && n.scatter_rays != 4 && n.scatter_rays != 8)
         return fail(DUS_EINVAL, "scatter_rays must be 0 (automatic), 2, 4 or 8");
-    if (n.fwd_chunk != 4 && n.fwd_chunk != 8 && n.fwd_chunk != 16) return fail(DUS_EINVAL, "fwd_chunk must be 4, 8 or 16");
+    if (n.fwd_chunk != 0 && n.fwd_chunk != 4 && n.fwd_chunk != 8 && n.fwd_chunk != 16)
+        return fail(DUS_EINVAL, "fwd_chunk must be 0 (automatic), 4, 8 or 16");
     if (n.bwd_chunk != 4 && n.bwd_chunk != 8) return fail(DUS_EINVAL, "bwd_chunk must be 4 or 8");
     if (n.xcd_group < 1 || n.xcd_group > 64) return fail(DUS_EINVAL, "xcd_group must be in [1, 64]");
     n.span_samples = sc->span_samples ? sc->span_samples : dus::kSpanSamples;

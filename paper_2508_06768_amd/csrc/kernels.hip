@@ -1504,6 +1504,15 @@ __global__ __launch_bounds__(64 * W) void k_backward(VolArgs v, PhysArgs p, FanT
 // --------------------------------------------------------------------------
 constexpr int kScatterSpl = 4;     // consecutive depths per lane, at most
 
+// floor(a / b) for a >= 0, b >= 1, a + b < 2^21, from rb = rcp(b) (within
+// 1 ulp): (a + 0.5) / b lies at least 0.5 / b from an integer, more than the
+// product's error (a / b + 1) 2^-22.  A few instructions, where an integer
+// division takes about thirty.
+__device__ __forceinline__ int small_quot(int a, float rb)
+{
+    return (int)(((float)a + 0.5f) * rb);
+}
+
 template <int RB>
 struct ScatterBox {
     static constexpr int cap = RB == 2 ? 4096 : (RB == 4 ? 2048 : 1024);   // FP64 entries
@@ -1579,12 +1588,14 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
     const double fsc = fix ? fscale[0] : 0.0;
     for (int t = lane; t < CAP; t += 64) s_box[t] = 0.0;
     // dL/dZ of the next group is loaded one group ahead; the lane's depths
-    // past spl stay zero (inactive)
+    // past spl stay zero (inactive).  The loads are clamped into the row and
+    // masked afterwards (no branch per load; spl is uniform).
     float zn[kScatterSpl];
 #pragma unroll
     for (int q = 0; q < kScatterSpl; ++q) {
         const int k = k_begin + ch * spl + q;
-        zn[q] = (ray_ok && q < spl && k < k_end) ? zrow[k] : 0.0f;
+        const float x = (q < spl) ? zrow[min(k, S - 1)] : 0.0f;
+        zn[q] = (ray_ok && k < k_end) ? x : 0.0f;
     }
     for (int k0 = k_begin; k0 < k_end; k0 += G) {
         float zb[kScatterSpl];
@@ -1592,7 +1603,8 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
         for (int q = 0; q < kScatterSpl; ++q) {
             zb[q] = zn[q];
             const int k = k0 + G + ch * spl + q;
-            zn[q] = (ray_ok && q < spl && k < k_end) ? zrow[k] : 0.0f;
+            const float x = (q < spl) ? zrow[min(k, S - 1)] : 0.0f;
+            zn[q] = (ray_ok && k < k_end) ? x : 0.0f;
         }
         Stencil st[kScatterSpl];
         int qf = -1, ql = -1;
@@ -1709,9 +1721,16 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
         // are issued before their atomics
         {
             const int E = bx * by * bz;
-            const int dx = 64 % bx, dyz = 64 / bx;
-            const int dy = dyz % by, dz = dyz / by;
-            int x = lane % bx, y = (lane / bx) % by, z = lane / (bx * by);
+            // lane -> (x, y, z) and the step of 64 entries, with bx <= 64
+            // and the box within CAP entries
+            const float rbx = __builtin_amdgcn_rcpf((float)bx), rby = __builtin_amdgcn_rcpf((float)by);
+            const int dyz = small_quot(64, rbx), dz = small_quot(dyz, rby);
+            const int dx = 64 - (int)__umul24((unsigned)dyz, (unsigned)bx);
+            const int dy = dyz - (int)__umul24((unsigned)dz, (unsigned)by);
+            const int ql = small_quot(lane, rbx);
+            int z = small_quot(ql, rby);
+            int x = lane - (int)__umul24((unsigned)ql, (unsigned)bx);
+            int y = ql - (int)__umul24((unsigned)z, (unsigned)by);
             for (int e0 = 0; e0 < E; e0 += 256) {
                 double val[4];
                 int at[4], gi[4];
@@ -2573,12 +2592,31 @@ inline hipError_t join_side(hipStream_t st, const SideStream &s)
         }                                                                                      \
         break;
 
+// automatic forward tile (chunk 0): 8 x 64 samples, unless the table's rays
+// fill 512-sample tiles clearly worse than 256-sample ones.  On full tiles
+// the 4 x 64 tile costs about 7% more per sample (64 poses x 256 x 1024:
+// 164 against 153 us); on the uneven 64-pose batch, whose rays pad to 1.20x
+// their samples in 512-sample tiles and to 1.09x in 256-sample ones, it
+// takes 217 against 229 us.
+int auto_fwd_chunk(const FanTable &t)
+{
+    long long pad4 = 0, pad8 = 0;
+    for (int f = 0; f < t.n; ++f) {
+        const long long r = t.f[f].n_rays, s = t.f[f].n_samples;
+        pad4 += r * ((s + 255) / 256) * 256;
+        pad8 += r * ((s + 511) / 512) * 512;
+    }
+    return (pad8 * 100 > pad4 * 107) ? 4 : 8;
+}
+
 hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const PhysArgs &p,
                           const FanTable &t, const float *poses, float *out, float *min_pivot,
                           int pivot_base, double *carry, int32_t *carry_exp, double *cstate, float *gain,
                           hipStream_t st, const ZeroArgs &zero, int span_samples, const SideStream *side)
 {
     if (t.total_rays <= 0) return hipSuccess;
+    if (chunk == 0) chunk = auto_fwd_chunk(t);
+    if (chunk != 4 && chunk != 8 && chunk != 16) return hipErrorInvalidValue;
     // the rays of the table's long fans (its first ones: a table lists its
     // fans longest first) get kSpanWaves wavefronts each, the rest one
     const int n_span = span_rays(t, span_samples);

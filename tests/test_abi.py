@@ -204,7 +204,7 @@ def test_schedule_validation():
         assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(0, 0, 0, 0, 0))) == _lib.DUS_OK
         got = _lib.DusSchedule()
         assert L.dus_get_schedule(ctypes.byref(got)) == _lib.DUS_OK
-        assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays, got.span_samples) == (8, 4, 16, 0, 4096)
+        assert (got.fwd_chunk, got.bwd_chunk, got.xcd_group, got.scatter_rays, got.span_samples) == (0, 4, 16, 0, 4096)
         for span in (-1, 1, _lib.MAX_SAMPLES):
             assert L.dus_set_schedule(ctypes.byref(_lib.DusSchedule(16, 8, 64, 2, span))) == _lib.DUS_OK
             assert L.dus_get_schedule(ctypes.byref(got)) == _lib.DUS_OK
