@@ -870,9 +870,9 @@ int dus_plan_get_schedule(const dus_plan *p, dus_schedule *sc)
 }
 
 // ev (optional): DUS_NUM_PHASES + 1 events recorded at the phase boundaries
-static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const float *target, float *bmode,
-                        double *loss, float *grad_Z, float *grad_pose, void *ws, hipStream_t st,
-                        hipEvent_t *ev = nullptr)
+static int plan_enqueue_body(dus_plan *p, const float *Z, const float *poses, const float *target, float *bmode,
+                             double *loss, float *grad_Z, float *grad_pose, void *ws, hipStream_t st,
+                             hipEvent_t *ev, bool &forked)
 {
     auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
     const dus::VolArgs va = vol_args(Z, &p->vol);
@@ -931,6 +931,7 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     if (two) {
         DUS_HIP(hipEventRecord(p->side.fork, st), "fork event");
         DUS_HIP(hipStreamWaitEvent(p->side.st, p->side.fork, 0), "fork wait");
+        forked = true;
     }
     DUS_HIP(mark(DUS_PHASE_FORWARD), "event");
     if (fwd) {
@@ -1023,6 +1024,22 @@ static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const f
     DUS_HIP(dus::launch_finish(part, n_part, loss, acc, poses, n_poses, grad_pose, st), "loss and pose kernel");
     DUS_HIP(mark(DUS_NUM_PHASES), "event");
     return DUS_OK;
+}
+
+static int plan_enqueue(dus_plan *p, const float *Z, const float *poses, const float *target, float *bmode,
+                        double *loss, float *grad_Z, float *grad_pose, void *ws, hipStream_t st,
+                        hipEvent_t *ev = nullptr)
+{
+    bool forked = false;
+    const int s = plan_enqueue_body(p, Z, poses, target, bmode, loss, grad_Z, grad_pose, ws, st, ev, forked);
+    if (s != DUS_OK && forked) {
+        // the second stream is joined back also when a launch failed: a
+        // capture must not end with a fork left open, and the caller's
+        // stream must wait for what the second stream already holds
+        (void)hipEventRecord(p->side.join, p->side.st);
+        (void)hipStreamWaitEvent(st, p->side.join, 0);
+    }
+    return s;
 }
 
 int dus_plan_step(dus_plan *p, const float *Z, const float *poses, const float *target, float *bmode,

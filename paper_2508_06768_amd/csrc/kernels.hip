@@ -2638,7 +2638,12 @@ hipError_t launch_forward(int chunk, int xcd_group, const VolArgs &v, const Phys
         return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && sst != st) e = join_side(st, *side);
+    if (sst != st) {
+        // joined also after a failed launch: a capture must not end with a
+        // fork left open, and the caller's stream must wait for the side's work
+        const hipError_t ej = join_side(st, *side);
+        if (e == hipSuccess) e = ej;
+    }
     return e;
 }
 
@@ -2675,6 +2680,7 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
     if (t.total_rays <= 0) return hipSuccess;
     if (pose_acc && !pose_part) return hipErrorInvalidValue;
     if (zbar && !rays) return hipErrorInvalidValue;
+    if (chunk != 4 && chunk != 8) return hipErrorInvalidValue;
     const bool fused = (target != nullptr);
     const bool spk = p.speckle && !gain;      // recorded gains replace the speckle variates
     if (!carry) cstate = nullptr;             // chunk states are read in the frames of the carry records
@@ -2697,7 +2703,12 @@ hipError_t launch_adjoint(int chunk, int xcd_group, const VolArgs &v, const Phys
         return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && sst != st) e = join_side(st, *side);
+    if (sst != st) {
+        // joined also after a failed launch: a capture must not end with a
+        // fork left open, and the caller's stream must wait for the side's work
+        const hipError_t ej = join_side(st, *side);
+        if (e == hipSuccess) e = ej;
+    }
     return e;
 }
 

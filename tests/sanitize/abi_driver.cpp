@@ -13,6 +13,12 @@
 #include "../../include/diffus.h"
 
 extern int g_launches;
+extern "C" {
+void stub_fail_launch(long n);
+long stub_launches(void);
+int stub_unjoined_captures(void);
+long stub_open_work(void);
+}
 
 namespace {
 int failures = 0;
@@ -148,6 +154,42 @@ int main()
             }
         }
     dus_plan_destroy(nullptr);
+
+    // a launch that fails inside a two-chain step (captured, and eager): the
+    // step reports it, every fork into the second stream is joined back (the
+    // capture ends cleanly; eagerly, no work is left on the second stream
+    // that the caller's stream does not wait for), and the plan then steps
+    // as before
+    {
+        const dus_physics pf = physics(1, 1);
+        std::vector<dus_fan> ff = fans(4, 5, 100);
+        for (int flags : {0, (int)DUS_PLAN_NO_GRAPH, (int)(DUS_PLAN_NO_GRAPH | DUS_PLAN_POSE_ONLY)}) {
+            dus_plan *plan = nullptr;
+            expect(dus_plan_create(&plan, &v, ff.data(), 4, &pf, flags) == DUS_OK, "plan create (failures)");
+            const int64_t wsp = dus_plan_workspace_bytes(plan);
+            uintptr_t img = kImg;
+            auto step = [&]() {
+                img += 0x1000;              // a new image pointer: the graph is captured again
+                return dus_plan_step(plan, dev<float>(kZ), dev<float>(kPoses), dev<float>(kImg + 0x800000),
+                                     dev<float>(img), dev<double>(kGrad),
+                                     (flags & DUS_PLAN_POSE_ONLY) ? nullptr : dev<float>(kGrad + 0x200000),
+                                     dev<float>(kGrad + 0x100000), dev<void>(kWs), (size_t)wsp, nullptr);
+            };
+            const long l0 = stub_launches();
+            expect(step() == DUS_OK, "step before failures");
+            const long per_step = stub_launches() - l0;
+            expect(per_step >= 8, "a two-chain step launches its kernels");
+            for (long k = 1; k <= per_step; ++k) {
+                stub_fail_launch(k);
+                expect(step() == DUS_EHIP, "failed launch reported");
+                stub_fail_launch(0);
+                expect(stub_unjoined_captures() == 0, "capture ended with every fork joined");
+                expect(stub_open_work() == 0, "no work left unjoined on the second stream");
+                expect(step() == DUS_OK, "step after a failed one");
+            }
+            dus_plan_destroy(plan);
+        }
+    }
 
     // invalid requests: a negative status, nothing launched
     const dus_physics p = physics(1, 1);
