@@ -1,0 +1,90 @@
+"""Seeded random configurations against the FP64 oracle.
+
+Each case draws a volume (non-cubic, anisotropic spacing, shifted origin),
+one to four poses with their own fans (1-40 rays, 1-2000 samples that end
+in the volume or run on past it, steps of 0.05-1.5 mm, apertures up to
+1.5 rad, apexes near or past the volume's edge), the physics (both
+reflection conventions, every attenuation mode, speckle and blur on or
+off) and a schedule (forward and adjoint tiles,
+rays per scatter wavefront, XCD grouping, the ray length from which several
+wavefronts share a ray).  It then checks, at the bars of the other parity
+tests: the rendered images, the adjoint of a random dL/dI (dL/dZ and
+dL/dpose), and the fused step (images, loss, dL/dZ, dL/dpose) against a
+target rendered at perturbed poses.
+"""
+import numpy as np
+import pytest
+
+from paper_2508_06768_amd import synth
+from tests import helpers as H
+from tests.test_gpu_parity import (_check_images, _check_plan, _gpu, _plan_reference, _run_plan,
+                                   check_grad_pose, check_grad_volume)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def random_case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(20, 41))
+    Z = synth.brain_volume(seed, n, 1.0, semi_range=(2.0, 0.3 * n))
+    nz, ny, nx = (int(rng.integers(8, n + 1)) for _ in range(3))
+    Z = np.ascontiguousarray(Z[:nz, :ny, :nx])
+    spacing = tuple(float(s) for s in rng.uniform(0.6, 1.4, 3))
+    origin = tuple(float(o) for o in rng.uniform(-2.0, 2.0, 3))
+    ext = np.array([nx * spacing[0], ny * spacing[1], nz * spacing[2]])
+    P = int(rng.integers(1, 5))
+    poses, fans = [], []
+    for p in range(P):
+        c = np.array(origin) + ext * np.array([rng.uniform(0.2, 0.8), rng.uniform(0.2, 0.8), rng.uniform(-0.1, 0.3)])
+        poses.append([*c, *rng.uniform(-0.4, 0.4, 3)])
+        n_rays = int(rng.choice([1, 2, int(rng.integers(3, 41))]))
+        ds = float(rng.choice([rng.uniform(0.05, 0.3), rng.uniform(0.3, 1.5)]))
+        # rays that end in the volume, or run on past it (clamped samples;
+        # several tiles, and several wavefronts per ray from 512 samples)
+        n_fit = int(1.3 * ext.max() / ds) + 2
+        n_samples = int(rng.integers(1, min(n_fit, 2000) + 1) if rng.integers(0, 2) else rng.integers(600, 2001))
+        fans.append(synth.FanSpec(n_rays, n_samples, float(rng.uniform(0.0, 1.5)), ds,
+                                  float(rng.uniform(0.0, 3.0)), p))
+    phys = synth.PhysicsSpec(refl_mode=int(rng.integers(0, 2)), atten_mode=int(rng.integers(0, 3)),
+                             speckle_on=bool(rng.integers(0, 2)), blur_on=bool(rng.integers(0, 2)),
+                             alpha=float(rng.uniform(0.3, 1.0)), freq=float(rng.uniform(3.0, 7.0)),
+                             seed=int(rng.integers(1 << 40)))
+    sched = {"fwd_chunk": int(rng.choice([0, 4, 8, 16])), "bwd_chunk": int(rng.choice([4, 8])),
+             "scatter_rays": int(rng.choice([0, 2, 4, 8])), "xcd_group": int(rng.choice([1, 4, 16, 64])),
+             "span_samples": int(rng.choice([-1, 0, 512, 1024]))}
+    shift = np.concatenate([rng.uniform(-0.5, 0.5, 3), rng.uniform(-0.03, 0.03, 3)]).astype(np.float32)
+    case = synth.Case(f"random{seed}", Z, spacing, origin, np.asarray(poses, np.float32), fans, phys)
+    return case, sched, shift
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_configuration(seed):
+    from paper_2508_06768_amd.render import get_schedule, render, render_backward, set_schedule
+    case, sched, shift = random_case(seed)
+    print("case", seed, case.Z.shape, case.spacing, [(f.n_rays, f.n_samples, round(f.ds, 3)) for f in case.fans],
+          case.phys, sched, flush=True)
+    geom, Z, P = _gpu(case)
+    ref_img = H.oracle_render(case)
+    old = get_schedule()
+    try:
+        set_schedule(**sched)
+        img = render(Z, P, geom).cpu().numpy()
+        if np.abs(ref_img).max() > 0:
+            _check_images(img, ref_img, f"random {seed} render", case.fans)
+        else:
+            assert np.all(img == 0)
+        w = np.random.default_rng(seed).standard_normal(geom.total).astype(np.float32)
+        gZ, gp = render_backward(Z, P, geom, torch.from_numpy(w).to(DEV))
+        rV, rp = H.oracle_backward(case, w.astype(np.float64))
+        if np.abs(rV).max() > 0:
+            check_grad_volume(gZ.cpu().numpy(), rV, f"random {seed} backward")
+        else:
+            assert np.all(gZ.cpu().numpy() == 0)
+        check_grad_pose(gp.cpu().numpy(), rp, f"random {seed} backward")
+    finally:
+        set_schedule(**old)
+    target = H.oracle_render(case, poses=case.poses + shift[None, :])
+    _check_plan(case, _run_plan(case, target, sched, replays=2), _plan_reference(case, target), f"random {seed} plan")
