@@ -1598,12 +1598,15 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
         zn[q] = (ray_ok && k < k_end) ? x : 0.0f;
     }
     for (int k0 = k_begin; k0 < k_end; k0 += G) {
+        // the segment's last group loads nothing ahead (the next segment
+        // belongs to another wavefront)
+        const bool ahead = k0 + G < k_end;
         float zb[kScatterSpl];
 #pragma unroll
         for (int q = 0; q < kScatterSpl; ++q) {
             zb[q] = zn[q];
             const int k = k0 + G + ch * spl + q;
-            const float x = (q < spl) ? zrow[min(k, S - 1)] : 0.0f;
+            const float x = (ahead && q < spl) ? zrow[min(k, S - 1)] : 0.0f;
             zn[q] = (ray_ok && k < k_end) ? x : 0.0f;
         }
         Stencil st[kScatterSpl];
