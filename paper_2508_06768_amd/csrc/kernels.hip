@@ -1730,10 +1730,10 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
             const int dyz = small_quot(64, rbx), dz = small_quot(dyz, rby);
             const int dx = 64 - (int)__umul24((unsigned)dyz, (unsigned)bx);
             const int dy = dyz - (int)__umul24((unsigned)dz, (unsigned)by);
-            const int ql = small_quot(lane, rbx);
-            int z = small_quot(ql, rby);
-            int x = lane - (int)__umul24((unsigned)ql, (unsigned)bx);
-            int y = ql - (int)__umul24((unsigned)z, (unsigned)by);
+            const int yz = small_quot(lane, rbx);
+            int z = small_quot(yz, rby);
+            int x = lane - (int)__umul24((unsigned)yz, (unsigned)bx);
+            int y = yz - (int)__umul24((unsigned)z, (unsigned)by);
             for (int e0 = 0; e0 < E; e0 += 256) {
                 double val[4];
                 int at[4], gi[4];
@@ -2601,7 +2601,7 @@ inline hipError_t join_side(hipStream_t st, const SideStream &s)
 // 164 against 153 us); on the uneven 64-pose batch, whose rays pad to 1.20x
 // their samples in 512-sample tiles and to 1.09x in 256-sample ones, it
 // takes 217 against 229 us.
-int auto_fwd_chunk(const FanTable &t)
+static int auto_fwd_chunk(const FanTable &t)
 {
     long long pad4 = 0, pad8 = 0;
     for (int f = 0; f < t.n; ++f) {
