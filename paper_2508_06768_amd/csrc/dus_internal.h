@@ -25,7 +25,7 @@ struct FanRec {
     int32_t pose;           // row of the poses array
     int32_t pivot_begin;    // pose-major index of this fan's first ray
     int32_t carry_begin;    // first tile-carry record of this fan's first ray
-    int32_t pad_;
+    int32_t unit_begin;     // first wavefront of this fan in a scatter launch (set by launch_scatter)
 };
 static_assert(sizeof(FanRec) == 56, "FanRec layout");
 

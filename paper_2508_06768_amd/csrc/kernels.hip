@@ -1541,18 +1541,22 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
     // each with its ceil(n_samples / seg) segments of ray blocks (ray blocks
     // fastest: neighbouring wavefronts share voxels).  Two-dimensional grid:
     // the ray blocks of all fans along x, the segment along y (a fan's
-    // blocks past its depth exit at once).
+    // blocks past its depth exit at once).  The launcher records each fan's
+    // first block in unit_begin.
     const int b = remap_block(blockIdx.x, gridDim.x, xgrp);
     const bool two_d = gridDim.y > 1;
     const int seg = 1 << seg_shift;              // a power of two: no division per fan
-    int fi = 0, acc = 0, nrb = 1;
-    for (;; ++fi) {
-        nrb = (tab.f[fi].n_rays + RB - 1) / RB;
-        const int nb = two_d ? nrb : nrb * ((tab.f[fi].n_samples + seg - 1) >> seg_shift);
-        if (b < acc + nb || fi + 1 == tab.n) break;
-        acc += nb;
+    int fi = 0;
+    {
+        // the fan whose wavefronts hold b: binary search over the fans' first units
+        int hi = tab.n - 1;
+        while (fi < hi) {
+            const int mid = (fi + hi + 1) >> 1;
+            if (tab.f[mid].unit_begin <= b) fi = mid; else hi = mid - 1;
+        }
     }
     const FanRec fr = tab.f[fi];
+    const int acc = fr.unit_begin, nrb = (fr.n_rays + RB - 1) / RB;
     const int sgi = two_d ? (int)blockIdx.y : (b - acc) / nrb;
     const int j = (b - acc - (two_d ? 0 : sgi * nrb)) * RB + slot;
     const bool ray_ok = j < fr.n_rays;
@@ -2762,19 +2766,27 @@ hipError_t launch_scatter(int scatter_rays, int xcd_group, const VolArgs &v, con
     }
     const long long nseg_max = (smax + seg - 1) / seg;
     const long long grid2 = nrb_all * nseg_max;
-    const dim3 grid = (grid2 > nunits && grid2 <= 2 * nunits) ? dim3((unsigned)nrb_all, (unsigned)nseg_max)
-                                                              : dim3((unsigned)nunits);
+    const bool two_d = grid2 > nunits && grid2 <= 2 * nunits;
+    const dim3 grid = two_d ? dim3((unsigned)nrb_all, (unsigned)nseg_max) : dim3((unsigned)nunits);
+    // each fan's first wavefront (along x for the 2-D grid)
+    FanTable ts = t;
+    long long u = 0;
+    for (int f = 0; f < t.n; ++f) {
+        ts.f[f].unit_begin = (int32_t)u;
+        const long long nrb = (t.f[f].n_rays + scatter_rays - 1) / scatter_rays;
+        u += two_d ? nrb : nrb * ((t.f[f].n_samples + seg - 1) / seg);
+    }
     switch (scatter_rays) {
     case 2:
-        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg_shift, xcd_group,
+        hipLaunchKernelGGL((k_scatter<2>), grid, dim3(64), 0, st, v, ts, rays, zbar, gZ, seg_shift, xcd_group,
                            fix, fscale);
         break;
     case 4:
-        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg_shift, xcd_group,
+        hipLaunchKernelGGL((k_scatter<4>), grid, dim3(64), 0, st, v, ts, rays, zbar, gZ, seg_shift, xcd_group,
                            fix, fscale);
         break;
     case 8:
-        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, t, rays, zbar, gZ, seg_shift, xcd_group,
+        hipLaunchKernelGGL((k_scatter<8>), grid, dim3(64), 0, st, v, ts, rays, zbar, gZ, seg_shift, xcd_group,
                            fix, fscale);
         break;
     default:
