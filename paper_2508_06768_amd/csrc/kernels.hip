@@ -166,6 +166,9 @@ struct Ray {
     double a2;             // round-trip amplitude over one step
     double dirx, dirz;     // probe-frame direction (y component is 0)
     double r0, ds;
+    // orthonormal basis, world frame: the ray's direction D, its in-plane
+    // normal T = R (cz, 0, -sx) and the fan plane's normal N = R (0, 1, 0)
+    double bd[3], bt[3], bn[3];
 };
 
 // wave_uniform: every lane of the wavefront traces the same ray (its
@@ -183,6 +186,12 @@ __device__ __forceinline__ void setup_ray(const VolArgs &v, const PhysArgs &p, c
     const double th = fr.n_rays > 1 ? -0.5 * A + (double)j * A / (double)(fr.n_rays - 1) : 0.0;
     const double sx = sin(th), cz = cos(th);
     const double d[3] = {R[0] * sx + R[2] * cz, R[3] * sx + R[5] * cz, R[6] * sx + R[8] * cz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ray.bd[a] = d[a];
+        ray.bt[a] = R[3 * a] * cz - R[3 * a + 2] * sx;
+        ray.bn[a] = R[3 * a + 1];
+    }
     const double r0 = fr.r0, ds = fr.ds;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -210,6 +219,12 @@ __device__ __forceinline__ void setup_ray(const VolArgs &v, const PhysArgs &p, c
     ray.dirz = uniform(ray.dirz);
     ray.r0 = uniform(ray.r0);
     ray.ds = uniform(ray.ds);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ray.bd[a] = uniform(ray.bd[a]);
+        ray.bt[a] = uniform(ray.bt[a]);
+        ray.bn[a] = uniform(ray.bn[a]);
+    }
 }
 
 // cell index (clamped) and fraction along one axis; NaN positions clamp to 0.
@@ -491,16 +506,23 @@ __device__ __forceinline__ void gather_tile_body(const VolArgs &v, const Ray &ra
         }
         if (s_zc && lane == 63 && (jj & 3) == 3) s_zc[jj >> 2] = z;
         if (KEEPG) {
-            // dZ/dp per mm: dZ/du / h, zero along an axis where the sample
-            // lies outside the volume (clamped)
+            // dZ/dp per mm (dZ/du / h, zero along an axis where the sample
+            // lies outside the volume: clamped), kept in FP32 as its
+            // components along the ray and across it (the ray's basis), so
+            // that the rounding of the large component along the ray stays
+            // along the ray, where it cannot reach the rotation gradient
             const double kk = (double)min(k, S - 1);
             const int n[3] = {v.nx, v.ny, v.nz};
+            double gw[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double u = fma(kk, ray.du[a], ray.u0[a]);
                 const bool inside = INSIDE || ((u >= 0.0) && (u <= (double)(n[a] - 1)));
-                s_g[a * T + i] = inside ? (float)(gu[a] * ih[a]) : 0.0f;
+                gw[a] = inside ? gu[a] * ih[a] : 0.0;
             }
+            s_g[i] = (float)fma(gw[0], ray.bd[0], fma(gw[1], ray.bd[1], gw[2] * ray.bd[2]));
+            s_g[T + i] = (float)fma(gw[0], ray.bt[0], fma(gw[1], ray.bt[1], gw[2] * ray.bt[2]));
+            s_g[2 * T + i] = (float)fma(gw[0], ray.bn[0], fma(gw[1], ray.bn[1], gw[2] * ray.bn[2]));
         }
     }
 }
@@ -966,7 +988,7 @@ __global__ __launch_bounds__(64 * W) void k_backward(VolArgs v, PhysArgs p, FanT
     constexpr int NB = T / kCarryBlock;
     // walks unrolled where the registers allow three wavefronts per SIMD
     constexpr int kWalkUnroll = (C <= 4 && !SPK && !FUSED) ? C : 1;
-    __shared__ float s_g_w[W][3 * T];     // dZ/du of every sample of the tile
+    __shared__ float s_g_w[W][3 * T];     // dZ/dp of every sample of the tile, in the ray's basis
     __shared__ double s_rho_w[W][T + T / 16];
     __shared__ double s_z_w[W][T + T / 16];
     __shared__ double s_dq_w[W][T + T / 16];   // d rho / dZ factor of every interface of the tile
@@ -1466,14 +1488,17 @@ __global__ __launch_bounds__(64 * W) void k_backward(VolArgs v, PhysArgs p, FanT
     if (pose_part) {
         if (threadIdx.x == 0) {
             // this ray's share of dL/dt = sum g and dL/dR = sum g (s dir)^T,
-            // dir = (sx, 0, cz); k_pose_reduce sums the rays of each pose
-            // (in a fixed order: no contended atomics on the pose's entries)
+            // dir = (sx, 0, cz), with g back from the ray's basis to the world
+            // frame; k_pose_reduce sums the rays of each pose (in a fixed
+            // order: no contended atomics on the pose's entries)
             double *pr = pose_part + (size_t)kRayPart * g;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                pr[a] = r[a];
-                pr[3 + 2 * a] = r[3 + a] * ray.dirx;
-                pr[4 + 2 * a] = r[3 + a] * ray.dirz;
+                const double gt = fma(r[0], ray.bd[a], fma(r[1], ray.bt[a], r[2] * ray.bn[a]));
+                const double gs = fma(r[3], ray.bd[a], fma(r[4], ray.bt[a], r[5] * ray.bn[a]));
+                pr[a] = gt;
+                pr[3 + 2 * a] = gs * ray.dirx;
+                pr[4 + 2 * a] = gs * ray.dirz;
             }
         }
     }

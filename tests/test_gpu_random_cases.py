@@ -10,7 +10,8 @@ rays per scatter wavefront, XCD grouping, the ray length from which several
 wavefronts share a ray).  It then checks, at the bars of the other parity
 tests: the rendered images, the adjoint of a random dL/dI (dL/dZ and
 dL/dpose), and the fused step (images, loss, dL/dZ, dL/dpose) against a
-target rendered at perturbed poses.
+target rendered at perturbed poses.  (Seeds 12-211 also passed, run once
+outside the suite.)
 """
 import numpy as np
 import pytest
@@ -60,7 +61,10 @@ def random_case(seed):
     return case, sched, shift
 
 
-@pytest.mark.parametrize("seed", range(12))
+# seed 128: a one-ray fan of 1425 samples beside a 2 x 12 fan, whose rotation
+# gradient is a small difference of large sums (it missed the pose bar, 1.2e-5,
+# while dZ/dp was kept in FP32 along the world axes)
+@pytest.mark.parametrize("seed", [*range(40), 128])
 def test_random_configuration(seed):
     from paper_2508_06768_amd.render import get_schedule, render, render_backward, set_schedule
     case, sched, shift = random_case(seed)
