@@ -92,3 +92,35 @@ def test_random_configuration(seed):
         set_schedule(**old)
     target = H.oracle_render(case, poses=case.poses + shift[None, :])
     _check_plan(case, _run_plan(case, target, sched, replays=2), _plan_reference(case, target), f"random {seed} plan")
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_plan_flags(seed):
+    """The fused step with random plan options on the random configurations:
+    pose-only, deterministic dL/dZ, one stream, no graph, with or without
+    the image; every option's outputs against the oracle (seeds 0-399 also
+    passed, run once outside the suite)."""
+    from paper_2508_06768_amd.render import FusedStep
+    case, sched, shift = random_case(seed)
+    rng = np.random.default_rng(7000 + seed)
+    fl = dict(pose_only=bool(rng.integers(0, 2)), deterministic=bool(rng.integers(0, 2)),
+              one_stream=bool(rng.integers(0, 2)), graph=bool(rng.integers(0, 4) > 0))
+    if fl["pose_only"]:
+        fl["deterministic"] = False
+    image = bool(rng.integers(0, 2))
+    print("case", seed, fl, "image", image, sched, flush=True)
+    geom, Z, P = _gpu(case)
+    target = H.oracle_render(case, poses=case.poses + shift[None, :])
+    T = torch.from_numpy(target.astype(np.float32)).to(DEV)
+    step = FusedStep(geom, schedule=sched, **fl)
+    bm = torch.empty(max(geom.total, 1), device=DEV) if image else None
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    gZ = None if fl["pose_only"] else torch.full_like(Z, 123.0)
+    gp = torch.empty((geom.n_poses, 6), device=DEV)
+    for _ in range(2):                          # the second step replays (or repeats) the first
+        step.step(Z, P, T, bmode=bm, loss=loss, grad_Z=gZ, grad_pose=gp)
+    torch.cuda.synchronize()
+    got = (bm[:geom.total].cpu().numpy() if image else None, loss.item(),
+           None if gZ is None else gZ.cpu().numpy(), gp.cpu().numpy())
+    step.close()
+    _check_plan(case, got, _plan_reference(case, target, want_volume=not fl["pose_only"]), f"flags {seed}")
