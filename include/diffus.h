@@ -128,7 +128,8 @@ int64_t dus_workspace_bytes(const dus_volume *vol, const dus_fan *fans, int32_t 
  *   ray_min_pivot  device, FP32 [total rays] in pose-major ray order, or
  *            NULL.  Per ray: min_k |P_{k+1}[1][1] / P_k[1][1]|, the pivots of
  *            the top-down elimination of the truncated systems (ratios of
- *            consecutive determinants of Eq. 4); 0 means a singular system.
+ *            consecutive determinants of Eq. 4); 0 means a singular system,
+ *            and a ray of one sample (no interface) reports +inf.
  *   ws       device workspace of at least dus_workspace_bytes(..., 0) bytes
  *            (may be NULL when that size is 0)
  */

@@ -75,7 +75,10 @@ def test_random_configuration(seed):
     old = get_schedule()
     try:
         set_schedule(**sched)
-        img = render(Z, P, geom).cpu().numpy()
+        img, piv = render(Z, P, geom, want_pivot=True)
+        img = img.cpu().numpy()
+        # the rays' smallest pivots (+inf for a ray of one sample)
+        np.testing.assert_allclose(piv.cpu().numpy(), H.oracle_render(case, want_pivot=True)[1], rtol=1e-5)
         if np.abs(ref_img).max() > 0:
             _check_images(img, ref_img, f"random {seed} render", case.fans)
         else:
