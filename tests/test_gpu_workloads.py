@@ -414,6 +414,36 @@ def test_edge_sizes():
                     _plan_reference(case, target, want_volume=False), "edge pose-only plan")
 
 
+def test_largest_fan():
+    """One fan of DUS_MAX_RAYS (65536) rays: render, adjoint and the fused
+    step against the oracle (64 samples per ray over a 48^3 volume, speckle
+    and blur on; 4.2 M ray-samples in one fan, so ray, blur-block and
+    scatter-block indices reach their largest per-fan values).  Signed
+    coefficients: with |R| this geometry has rays next to a pole (images
+    near 3e5), whose conditioning is not what is tested here."""
+    from paper_2508_06768_amd import _lib
+    from paper_2508_06768_amd.render import render, render_backward
+    n_rays = _lib.MAX_RAYS
+    Z = synth.brain_volume(31, 48, 1.0, semi_range=(3.0, 10.0))
+    case = synth.Case("largest_fan", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0),
+                      np.array([[23.5, 24.0, 0.0, 0.05, -0.04, 0.1]], np.float32),
+                      [synth.FanSpec(n_rays, 64, 1.4, 0.6, 2.0, 0)],
+                      synth.PhysicsSpec(refl_mode=1, speckle_on=True, blur_on=True, seed=31))
+    geom, Zt, P = _gpu(case)
+    print("largest fan", n_rays, "x 64", flush=True)
+    img = render(Zt, P, geom).cpu().numpy()
+    rep = H.parity_report(img, H.oracle_render(case))
+    print(rep, flush=True)
+    assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
+    w = np.random.default_rng(31).standard_normal(geom.total).astype(np.float32)
+    gZ, gp = render_backward(Zt, P, geom, torch.from_numpy(w).to(DEV))
+    rV, rp = H.oracle_backward(case, w.astype(np.float64))
+    check_grad_volume(gZ.cpu().numpy(), rV, "largest fan")
+    check_grad_pose(gp.cpu().numpy(), rp, "largest fan")
+    target = H.oracle_render(case, poses=case.poses + np.float32([[0.3, -0.2, 0.1, 0.01, 0.0, 0.0]]))
+    _check_plan(case, _run_plan(case, target, replays=2), _plan_reference(case, target), "largest fan plan")
+
+
 def test_registration_loop():
     """Pose-only fused steps under a graph give the same pose gradient as the
     separate forward / MSE / adjoint calls, and Adam on the poses reduces the
