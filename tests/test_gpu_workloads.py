@@ -471,6 +471,35 @@ def test_tall_volume():
     _check_plan(case, _run_plan(case, target, replays=2), _plan_reference(case, target), "tall volume plan")
 
 
+def test_wide_slices():
+    """A 4000 x 4000 x 2 volume (slices of 1.6e7 voxels, just under the 2^24
+    that the 24-bit index products allow) with fans lying in its mid-plane,
+    rays up to 3950 mm long across it: render, adjoint and the fused step
+    against the oracle.  The rotation by 120 degrees about (1, 1, 1) turns
+    the probe's depth axis into x and its lateral axis into y."""
+    from paper_2508_06768_amd.render import render, render_backward
+    rng = np.random.default_rng(43)
+    Z = rng.uniform(1.4, 1.8, size=(2, 4000, 4000)).astype(np.float32)
+    w0 = 2.0 * np.pi / 3.0 / np.sqrt(3.0)
+    case = synth.Case("wide", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0),
+                      np.array([[5.0, 5.0, 0.5, w0, w0, w0], [8.0, 2000.0, 0.5, w0, w0, w0]], np.float32),
+                      [synth.FanSpec(9, 7900, 0.5, 0.5, 0.0, 0), synth.FanSpec(4, 3000, 0.2, 1.2, 2.0, 1)],
+                      synth.PhysicsSpec(refl_mode=1, alpha=0.01, speckle_on=True, blur_on=True, seed=43))
+    geom, Zt, P = _gpu(case)
+    print("wide slices", Z.shape, flush=True)
+    img = render(Zt, P, geom).cpu().numpy()
+    rep = H.parity_report(img, H.oracle_render(case))
+    print(rep, flush=True)
+    assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
+    w = np.random.default_rng(43).standard_normal(geom.total).astype(np.float32)
+    gZ, gp = render_backward(Zt, P, geom, torch.from_numpy(w).to(DEV))
+    rV, rp = H.oracle_backward(case, w.astype(np.float64))
+    check_grad_volume(gZ.cpu().numpy(), rV, "wide slices")
+    check_grad_pose(gp.cpu().numpy(), rp, "wide slices")
+    target = H.oracle_render(case, poses=case.poses + np.float32([[0.3, -0.2, 0.0, 0.0, 0.0, 0.0]]))
+    _check_plan(case, _run_plan(case, target, replays=2), _plan_reference(case, target), "wide slices plan")
+
+
 def test_registration_loop():
     """Pose-only fused steps under a graph give the same pose gradient as the
     separate forward / MSE / adjoint calls, and Adam on the poses reduces the
