@@ -500,6 +500,57 @@ def test_wide_slices():
     _check_plan(case, _run_plan(case, target, replays=2), _plan_reference(case, target), "wide slices plan")
 
 
+def test_images_past_2_31_pixels():
+    """65 poses of 4096 rays x 8192 samples over the 256^3 volume: 2.18e9
+    pixels, so the last pose's image starts at pixel 2^31 (64-bit offsets
+    through render, blur, adjoint and the pose sums; rays of 8192 samples
+    also take several wavefronts each).  Checked one pose at a time, where
+    the oracle can follow: the first and the last pose's images from the
+    render, and their pose gradients and the loss terms of a pose-only
+    fused step against a zero target."""
+    from paper_2508_06768_amd.render import FusedStep, render
+    B = 65
+    Z = synth.brain256(1002)
+    poses = synth.random_poses(np.random.default_rng(1007), B, 255.0).astype(np.float32)
+    fans = [synth.FanSpec(4096, 8192, 1.2, 0.03, 0.0, p) for p in range(B)]
+    # signed coefficients: with |R| some of these 246 mm rays come near a
+    # pole, whose conditioning is tested elsewhere
+    phys = synth.PhysicsSpec(refl_mode=1, speckle_on=True, blur_on=True, seed=1007)
+    case = synth.Case("past_2_31", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses, fans, phys)
+    geom, Zt, P = _gpu(case)
+    assert int(geom.offsets[B - 1]) >= 2 ** 31
+    print("images past 2^31 pixels:", geom.total, flush=True)
+    img = render(Zt, P, geom)
+
+    def one(p):
+        return synth.Case(f"pose{p}", Z, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), poses[p:p + 1],
+                          [synth.FanSpec(4096, 8192, 1.2, 0.03, 0.0, p)], phys)
+
+    for p in (0, B - 1):
+        rep = H.parity_report(geom.image(img, p).cpu().numpy().reshape(-1), H.oracle_render(one(p)))
+        print("pose", p, rep, flush=True)
+        assert rep["rel_l2"] <= 1e-5 and rep["max_abs_over_max"] <= 1e-5
+    del img
+    step = FusedStep(geom, pose_only=True)
+    T = torch.zeros(geom.total, dtype=torch.float32, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    gp = torch.empty((B, 6), device=DEV)
+    step.step(Zt, P, T, loss=loss, grad_pose=gp)
+    torch.cuda.synchronize()
+    step.close()
+    del T
+    gp = gp.cpu().numpy()
+    known = 0.0
+    for p in (0, B - 1):
+        _, ref_loss, _, rp = _plan_reference(one(p), np.zeros(4096 * 8192), want_volume=False)
+        check_grad_pose(gp[p:p + 1], rp, f"pose {p} of {B}")
+        known += ref_loss
+    # the loss is the sum of every pose's mean squared image: the two checked
+    # poses' terms bound it from below (the others are non-negative)
+    print("loss", loss.item(), "the two checked poses' terms", known, flush=True)
+    assert loss.item() >= known * (1.0 - 1e-5)
+
+
 def test_registration_loop():
     """Pose-only fused steps under a graph give the same pose gradient as the
     separate forward / MSE / adjoint calls, and Adam on the poses reduces the
