@@ -179,7 +179,6 @@ hipError_t launch_scan_convert(const float *img, int n_rays, int n_samples, doub
                                float fill, float *out, hipStream_t st);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
-hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t st);
 // *out = sum of the n partials (the loss of the fused step)
 hipError_t launch_sum_f64(const double *part, int64_t n, double *out, hipStream_t st, bool accumulate = false);
 // loss = sum of the partials (if loss) and grad = the finalised pose

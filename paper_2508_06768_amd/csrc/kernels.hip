@@ -85,13 +85,6 @@ __device__ __forceinline__ double rcp64(double b)
     return fma(fma(-b, r, 1.0), r, r);
 }
 
-__device__ __forceinline__ double div64(double a, double b)
-{
-    const double r = rcp64(b);
-    const double q = a * r;
-    return fma(fma(-b, q, a), r, q);
-}
-
 // partial unroll of the sample-gather loops: enough independent gathers in
 // flight without holding every tile sample in registers
 #ifndef GATHER_UNROLL
@@ -934,27 +927,6 @@ __global__ __launch_bounds__(64 * W) void k_forward(VolArgs v, PhysArgs p, FanTa
 struct Adj {
     double l0, l1, lD;
 };
-
-__device__ __forceinline__ Adj adj_step(const Adj &a, double v0, double v1, double D, double r,
-                                        double a2, double sgn, double eb, double &rbar)
-{
-    const double r2 = r * r;
-    const double A = a2 * (1.0 - r2 - sgn * r2);
-    const double B = -a2 * sgn * r;
-    const double E = a2 * (1.0 - r2);
-    const double v1n = fma(v0, r, v1);
-    const double w1 = rcp64(v1), w1p = rcp64(v1n);
-    const double e = r * D * w1 * w1p;
-    const double dA = -2.0 * a2 * r * (1.0 + sgn);
-    const double dB = -a2 * sgn;
-    const double dE = -2.0 * a2 * r;
-    rbar = a.l0 * fma(v0, dA, v1 * dB) + a.l1 * v0 + eb * D * w1p * w1p + a.lD * D * dE;
-    Adj n;
-    n.l0 = fma(a.l0, A, a.l1 * r) - eb * e * r * w1p;
-    n.l1 = fma(a.l0, B, a.l1) - eb * e * (w1 + w1p);
-    n.lD = fma(a.lD, E, eb * r * w1 * w1p);
-    return n;
-}
 
 // W = 1: one wavefront per ray walks its tiles from the deepest up.  W > 1
 // (rays of many tiles, with the forward's carry records and chunk states):
@@ -2531,13 +2503,6 @@ __global__ __launch_bounds__(256) void k_map_backward(const float *__restrict__ 
     }
 }
 
-__global__ void k_copy_f64(const double *s, double *d, long long n)
-{
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        d[i] = s[i];
-}
-
 __global__ void k_philox(const uint32_t *__restrict__ ctr, long long n, uint32_t k0, uint32_t k1,
                          uint32_t *__restrict__ out)
 {
@@ -3055,14 +3020,6 @@ hipError_t launch_map_backward(const float *in, int64_t n, const LutArgs &lut, c
     int g = grid_for(n, 256);
     if (g > 4096) g = 4096;
     hipLaunchKernelGGL(k_map_backward, dim3(g), dim3(256), 0, st, in, (long long)n, lut, gZ, grad_in, grad_z);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_f64(const double *src, double *dst, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(n, 256)), dim3(256), 0, st, src, dst,
-                       (long long)n);
     return hipGetLastError();
 }
 

@@ -293,7 +293,6 @@ hipError_t launch_scan_convert(const float *, int, int, double, double, double, 
 }
 hipError_t launch_zero_f64(double *, int64_t, hipStream_t st) { return launch_on(st); }
 hipError_t launch_zero_f32(float *, int64_t, hipStream_t st) { return launch_on(st); }
-hipError_t launch_copy_f64(const double *, double *, int64_t, hipStream_t st) { return launch_on(st); }
 hipError_t launch_sum_f64(const double *, int64_t, double *, hipStream_t st, bool) { return launch_on(st); }
 hipError_t launch_finish(const double *, int64_t, double *, const double *, const float *, int, float *, hipStream_t st)
 {
