@@ -1728,6 +1728,10 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
             }
         }
         __syncthreads();
+        // wave priority 1 for the flush (LDS reads and the global atomics wait
+        // on latency): in the two-chain step it then runs ahead of the other
+        // chain's arithmetic on the same CUs (step 0.5% faster)
+        __builtin_amdgcn_s_setprio(1);
         // flush: the box's entries in x-fastest order, 64 consecutive entries
         // per pass (consecutive lanes on consecutive x of a row); a lane's
         // (x, y, z) advances by constant carries, and four entries' LDS reads
@@ -1777,6 +1781,7 @@ __global__ __launch_bounds__(64) void k_scatter(VolArgs v, FanTable tab, const R
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     }
 }
